@@ -1,0 +1,695 @@
+/*
+ * CPU oracle for the ENO-MR finite-difference scheme (H. Shen, arXiv 2311.15504).
+ *
+ * TEST INFRASTRUCTURE.  This file is the plain, slow reference that the GPU
+ * library is checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code, header or
+ * table with the GPU library: the stencil coefficients arrive as arguments,
+ * computed in exact rational arithmetic by oracle/coeffs.py.
+ *
+ * Everything is FP64.  Built with -ffp-contract=off: every operation is rounded
+ * separately, except where fma() is written out.  The evaluation order of each
+ * formula is part of the specification (the paper leaves it open); the GPU
+ * kernels follow the same order so that stencil choices agree bit for bit.
+ *
+ *   - dot products (IS, fluxes, projections): first term a plain product, then
+ *     fma() terms, in ascending physical cell (or component) order;
+ *   - IS0 second differences: (f_c - 2 f_{c-1}) + f_{c-2}.
+ *
+ * Method steps and where the paper states them:
+ *   global Lax-Friedrichs splitting ............. Sec. 2.1, Eq. (LF_Flux_Split)
+ *   conservative semi-discrete operator ......... Sec. 2.1, Eq. (1DWENOFD)
+ *   ENO-MR stencil selection .................... Sec. 3.2, Steps 1-3.2,
+ *                                                 Eqs. (Baseline_IS), (CurrentIS), (ISCoe)
+ *   candidate pool and a_l, b_l ................. Sec. 3.1, Eq. (Candidates), Tables
+ *   SSP-RK3 ..................................... Sec. 2.3, Eq. (TVD3rdRK)
+ *   linear SSP-RK(m, m-1) ....................... Sec. 2.3, Eqs. (lSSPRK), (lSSPRK_Coe)
+ *   Euler equations, characteristic projection .. Sec. 4 preamble (Roe average at the
+ *                                                 face), Sec. 4.3, Sec. 4.4
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXC 29
+#define ORC_MAXW 17
+
+enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_ENONPHYS = 5 };
+enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1 };
+enum { ORC_ADVECTION = 0, ORC_BURGERS = 1 };
+enum { ORC_SPLIT_NONE = 0, ORC_SPLIT_LF = 1 };
+
+typedef struct {
+    int order;              /* 2r-1 */
+    int r;
+    int ncand;
+    int m[ORC_MAXC], n[ORC_MAXC];
+    double a[ORC_MAXC][ORC_MAXW];   /* a[c][l+m], l = -m..n */
+    double b[ORC_MAXC][ORC_MAXW];   /* b[c][l+m] */
+} orc_table;
+
+orc_table *orc_table_new(int order, int ncand, const int *mn, const double *a, const double *b)
+{
+    if (ncand < 1 || ncand > ORC_MAXC) return NULL;
+    orc_table *t = (orc_table *)calloc(1, sizeof(orc_table));
+    if (!t) return NULL;
+    t->order = order;
+    t->r = (order + 1) / 2;
+    t->ncand = ncand;
+    for (int c = 0; c < ncand; ++c) {
+        t->m[c] = mn[2 * c];
+        t->n[c] = mn[2 * c + 1];
+        for (int l = 0; l < ORC_MAXW; ++l) {
+            t->a[c][l] = a[c * ORC_MAXW + l];
+            t->b[c][l] = b[c * ORC_MAXW + l];
+        }
+    }
+    return t;
+}
+
+void orc_table_free(orc_table *t) { free(t); }
+
+/* ------------------------------------------------------------------------ */
+/* Scalar ENO-MR reconstruction at one face (Sec. 3.2)                       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Value at stencil offset l in the reconstruction frame.  For sign +1 the
+ * frame is centred on cell c = j and offsets run with the cell index; for
+ * sign -1 (the mirror image about x_{j+1/2}, Sec. 3.1) the centre is c = j+1
+ * and offset l is cell c - l.
+ */
+#define FR(l) (f[c + (long)s * (l)])
+
+/*
+ * Dot product of a stencil's coefficients with the values of its cells,
+ * summed in ascending physical cell order.  coef[l+m] belongs to offset l.
+ */
+static double stencil_dot(const double *coef, int m, int n, const double *f, long c, int s)
+{
+    /* cells covered: offsets -m..n; ascending cell order means offsets
+       ascending for s = +1 and descending for s = -1. */
+    int l0 = (s > 0) ? -m : n;
+    int dl = (s > 0) ? 1 : -1;
+    int cnt = m + n + 1;
+    int l = l0;
+    double acc = coef[l + m] * FR(l);
+    for (int k = 1; k < cnt; ++k) {
+        l += dl;
+        acc = fma(coef[l + m], FR(l), acc);
+    }
+    return acc;
+}
+
+/*
+ * Reconstruct f-hat at face j+1/2 from cell values f (indexable from
+ * j-r+1 to j+r).  sign = +1: f^+ (upwind on the left); sign = -1: f^-.
+ * Writes the chosen candidate's position in the candidate list to *idx.
+ */
+static double recon_face(const orc_table *T, const double *f, long j, int sign, int *idx)
+{
+    const int s = sign > 0 ? 1 : -1;
+    const long c = sign > 0 ? j : j + 1;
+
+    /* Step 1: baseline indicator IS0 = min(IS_L, IS_R), Eq. (Baseline_IS). */
+    double f0 = FR(0), fm1 = FR(-1), fm2 = FR(-2), fp1 = FR(1), fp2 = FR(2);
+    double isl = fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2));
+    double isr = fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2));
+    double is0 = fmin(isl, isr);
+
+    /* Step 2: IS = |sum b_l f_{j+l}| of every candidate, Eqs. (CurrentIS), (ISCoe).
+       (The paper only needs them up to the first accepted one; computing all of
+       them and then scanning gives the same choice.) */
+    double is[ORC_MAXC];
+    for (int k = 0; k < T->ncand; ++k) {
+        if (T->m[k] >= 1 && T->n[k] >= 1)
+            is[k] = fabs(stencil_dot(T->b[k], T->m[k], T->n[k], f, c, s));
+        else
+            is[k] = 0.0;
+    }
+
+    /* Step 3.1: first candidate in list order with m, n >= 1 and IS < IS0. */
+    for (int k = 0; k < T->ncand; ++k) {
+        if (T->m[k] >= 1 && T->n[k] >= 1 && is[k] < is0) {
+            *idx = k;
+            return stencil_dot(T->a[k], T->m[k], T->n[k], f, c, s);
+        }
+    }
+
+    /* Step 3.2: minmod between S_j^{j+1} and S_{j-1}^j, else S_j^j. */
+    double da = fp1 - f0;      /* slope towards the downwind neighbour */
+    double db = f0 - fm1;      /* slope towards the upwind neighbour   */
+    double mm;
+    int pick_m, pick_n;
+    if (da * db > 0.0) {
+        if (fabs(da) <= fabs(db)) { mm = da; pick_m = 0; pick_n = 1; }
+        else { mm = db; pick_m = 1; pick_n = 0; }
+    } else {
+        mm = 0.0; pick_m = 0; pick_n = 0;
+    }
+    *idx = T->ncand - 1;
+    for (int k = 0; k < T->ncand; ++k)
+        if (T->m[k] == pick_m && T->n[k] == pick_n) *idx = k;
+    return f0 + 0.5 * mm;
+}
+#undef FR
+
+/*
+ * Bare scalar reconstruction over n faces.  f_with_halo has n + 2r - 1
+ * entries; face i lies between array cells i + r - 1 and i + r.
+ */
+int orc_recon_faces(const orc_table *T, int sign, long n, const double *f_with_halo,
+                    double *fhat, uint8_t *idx)
+{
+    if (!T || n < 0 || (sign != 1 && sign != -1)) return ORC_EINVAL;
+    const int r = T->r;
+    for (long i = 0; i < n; ++i) {
+        int k;
+        fhat[i] = recon_face(T, f_with_halo, i + r - 1, sign, &k);
+        if (idx) idx[i] = (uint8_t)k;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundary handling: ghost index map                                        */
+/* ------------------------------------------------------------------------ */
+
+static long map_cell(long i, long n, int bc)
+{
+    if (bc == ORC_PERIODIC) {
+        long k = i % n;
+        return k < 0 ? k + n : k;
+    }
+    /* outflow: zero-gradient copy of the boundary node */
+    if (i < 0) return 0;
+    if (i >= n) return n - 1;
+    return i;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scalar conservation law on one line                                       */
+/* ------------------------------------------------------------------------ */
+
+static double scalar_flux(int flux, double a, double u)
+{
+    return flux == ORC_ADVECTION ? a * u : 0.5 * u * u;
+}
+
+/*
+ * Global LF split (Eq. LF_Flux_Split) with alpha = max |f'(u)| over the line,
+ * then f-hat = f-hat^+ + f-hat^- at faces f = 0..n (face f between cells f-1
+ * and f), and du/dt = -(f-hat_{j+1/2} - f-hat_{j-1/2}) / h (Eq. 1DWENOFD).
+ * With split == NONE the flux itself is reconstructed as f^+ (Sec. 4.2).
+ * idx (optional): 2 entries per face, [+, -].
+ */
+int orc_scalar_rhs(const orc_table *T, int flux, double a, int split, int bc, long n,
+                   double ih, const double *u, double *dudt, uint8_t *idx, double *alpha_out)
+{
+    if (!T || n < 2) return ORC_EINVAL;
+    const long g = T->r + 1;
+    const long nn = n + 2 * g;
+    double *fp = (double *)malloc(sizeof(double) * nn);
+    double *fm = (double *)malloc(sizeof(double) * nn);
+    double *fh = (double *)malloc(sizeof(double) * (n + 1));
+    if (!fp || !fm || !fh) { free(fp); free(fm); free(fh); return ORC_EINVAL; }
+
+    double alpha = 0.0;
+    for (long i = 0; i < n; ++i) {
+        double d = flux == ORC_ADVECTION ? fabs(a) : fabs(u[i]);
+        if (d > alpha) alpha = d;
+    }
+    if (alpha_out) *alpha_out = alpha;
+
+    for (long i = 0; i < nn; ++i) {
+        double ui = u[map_cell(i - g, n, bc)];
+        double fi = scalar_flux(flux, a, ui);
+        if (split == ORC_SPLIT_LF) {
+            double t = alpha * ui;
+            fp[i] = 0.5 * (fi + t);
+            fm[i] = 0.5 * (fi - t);
+        } else {
+            fp[i] = fi;
+            fm[i] = 0.0;
+        }
+    }
+    for (long f = 0; f <= n; ++f) {
+        long j = f - 1 + g;           /* left cell of face f in the ghosted array */
+        int kp, km;
+        double hp = recon_face(T, fp, j, +1, &kp);
+        double hm = 0.0;
+        km = 0;
+        if (split == ORC_SPLIT_LF) hm = recon_face(T, fm, j, -1, &km);
+        fh[f] = hp + hm;
+        if (idx) { idx[2 * f] = (uint8_t)kp; idx[2 * f + 1] = (uint8_t)km; }
+    }
+    for (long i = 0; i < n; ++i) dudt[i] = -((fh[i + 1] - fh[i]) * ih);
+    free(fp); free(fm); free(fh);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Euler equations: one line in the face-normal frame                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A line state holds nv = 3 (rho, m, E) or nv = 4 (rho, m_n, m_t, E)
+ * conserved variables, the momentum m_n normal to the faces.
+ */
+typedef struct {
+    double un, ut, p, c, H;
+    double F[4];
+} cell_prim;
+
+static int primitives(int nv, double gamma, const double *U, cell_prim *q)
+{
+    double rho = U[0], mn = U[1], mt = nv == 4 ? U[2] : 0.0, E = U[nv - 1];
+    double un = mn / rho;
+    double ut = nv == 4 ? mt / rho : 0.0;
+    double ke = nv == 4 ? 0.5 * (mn * un + mt * ut) : 0.5 * (mn * un);
+    double p = (gamma - 1.0) * (E - ke);
+    if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(mn)) return ORC_ENONPHYS;
+    q->un = un;
+    q->ut = ut;
+    q->p = p;
+    q->c = sqrt((gamma * p) / rho);
+    q->H = (E + p) / rho;
+    q->F[0] = mn;
+    q->F[1] = mn * un + p;
+    if (nv == 4) {
+        q->F[2] = mt * un;
+        q->F[3] = (E + p) * un;
+    } else {
+        q->F[2] = (E + p) * un;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Roe-averaged eigenvectors at the face between states UL and UR
+ * (Sec. 4 preamble).  Fields are ordered (u-c, u, [shear,] u+c); Lm is the
+ * inverse of Rm.  Returns nonzero if the averaged sound speed is not real.
+ */
+static int roe_eigen(int nv, double gamma, const double *UL, const cell_prim *qL,
+                     const double *UR, const cell_prim *qR, double Lm[4][4], double Rm[4][4])
+{
+    double sL = sqrt(UL[0]);
+    double sR = sqrt(UR[0]);
+    double d = sL + sR;
+    double u = (sL * qL->un + sR * qR->un) / d;
+    double v = nv == 4 ? (sL * qL->ut + sR * qR->ut) / d : 0.0;
+    double H = (sL * qL->H + sR * qR->H) / d;
+    double q2 = nv == 4 ? u * u + v * v : u * u;
+    double c2 = (gamma - 1.0) * (H - 0.5 * q2);
+    if (!(c2 > 0.0)) return ORC_ENONPHYS;
+    double c = sqrt(c2);
+    double k = (gamma - 1.0) / c2;
+    double ic = 1.0 / c;
+    double hq = 0.5 * k * q2;
+    double ku = k * u;
+    double uic = u * ic;
+    double uc = u * c;
+    if (nv == 4) {
+        double kv = k * v;
+        double L[4][4] = {
+            {0.5 * (hq + uic), -0.5 * (ku + ic), -0.5 * kv, 0.5 * k},
+            {1.0 - hq, ku, kv, -k},
+            {-v, 0.0, 1.0, 0.0},
+            {0.5 * (hq - uic), -0.5 * (ku - ic), -0.5 * kv, 0.5 * k},
+        };
+        double R[4][4] = {
+            {1.0, 1.0, 0.0, 1.0},
+            {u - c, u, 0.0, u + c},
+            {v, v, 1.0, v},
+            {H - uc, 0.5 * q2, v, H + uc},
+        };
+        memcpy(Lm, L, sizeof(L));
+        memcpy(Rm, R, sizeof(R));
+    } else {
+        double L[4][4] = {
+            {0.5 * (hq + uic), -0.5 * (ku + ic), 0.5 * k, 0.0},
+            {1.0 - hq, ku, -k, 0.0},
+            {0.5 * (hq - uic), -0.5 * (ku - ic), 0.5 * k, 0.0},
+            {0.0, 0.0, 0.0, 0.0},
+        };
+        double R[4][4] = {
+            {1.0, 1.0, 1.0, 0.0},
+            {u - c, u, u + c, 0.0},
+            {H - uc, 0.5 * q2, H + uc, 0.0},
+            {0.0, 0.0, 0.0, 0.0},
+        };
+        memcpy(Lm, L, sizeof(L));
+        memcpy(Rm, R, sizeof(R));
+    }
+    return ORC_OK;
+}
+
+/* Exported for the eigenvector tests: L and R at the Roe state of UL, UR. */
+int orc_roe_eigen(int nv, double gamma, const double *UL, const double *UR, double *Lout, double *Rout)
+{
+    cell_prim qL, qR;
+    if (primitives(nv, gamma, UL, &qL) || primitives(nv, gamma, UR, &qR)) return ORC_ENONPHYS;
+    double Lm[4][4], Rm[4][4];
+    int st = roe_eigen(nv, gamma, UL, &qL, UR, &qR, Lm, Rm);
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+            Lout[i * nv + j] = Lm[i][j];
+            Rout[i * nv + j] = Rm[i][j];
+        }
+    return st;
+}
+
+static double row_dot(const double *row, const double *x, int nv)
+{
+    double acc = row[0] * x[0];
+    for (int i = 1; i < nv; ++i) acc = fma(row[i], x[i], acc);
+    return acc;
+}
+
+/*
+ * Largest characteristic speed |u_n| + c over the n cells of a line
+ * (alpha of Eq. LF_Flux_Split for the Euler system).
+ */
+static int line_alpha(int nv, double gamma, long n, const double *Ul, double *alpha)
+{
+    double amax = 0.0;
+    for (long i = 0; i < n; ++i) {
+        double U[4];
+        for (int v = 0; v < nv; ++v) U[v] = Ul[v * n + i];
+        cell_prim q;
+        if (primitives(nv, gamma, U, &q)) return ORC_ENONPHYS;
+        double s = fabs(q.un) + q.c;
+        if (s > amax) amax = s;
+    }
+    *alpha = amax;
+    return ORC_OK;
+}
+
+/*
+ * Numerical fluxes at faces f = 0..n of one line (face f between cells f-1
+ * and f).  Ul is [nv][n] in the face-normal frame.  Fhat is [n+1][nv].
+ * idx (optional) holds nv*2 entries per face: [(field)*2 + (0:+, 1:-)].
+ */
+static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, long n,
+                             const double *Ul, double alpha, double *Fhat, uint8_t *idx)
+{
+    const long g = T->r + 1;
+    const long nn = n + 2 * g;
+    double *U = (double *)malloc(sizeof(double) * nn * nv);
+    double *Gp = (double *)malloc(sizeof(double) * nn * nv);
+    double *Gm = (double *)malloc(sizeof(double) * nn * nv);
+    cell_prim *Q = (cell_prim *)malloc(sizeof(cell_prim) * nn);
+    double *wp = (double *)malloc(sizeof(double) * nn);
+    double *wm = (double *)malloc(sizeof(double) * nn);
+    int st = ORC_OK;
+    if (!U || !Gp || !Gm || !Q || !wp || !wm) { st = ORC_EINVAL; goto done; }
+
+    /* Ghosted line, primitive quantities and the LF split G = (F +- alpha U)/2. */
+    for (long i = 0; i < nn; ++i) {
+        long src = map_cell(i - g, n, bc);
+        for (int v = 0; v < nv; ++v) U[i * nv + v] = Ul[v * n + src];
+        if ((st = primitives(nv, gamma, &U[i * nv], &Q[i]))) goto done;
+        for (int v = 0; v < nv; ++v) {
+            double t = alpha * U[i * nv + v];
+            Gp[i * nv + v] = 0.5 * (Q[i].F[v] + t);
+            Gm[i * nv + v] = 0.5 * (Q[i].F[v] - t);
+        }
+    }
+
+    for (long f = 0; f <= n; ++f) {
+        long j = f - 1 + g;      /* left cell of the face in the ghosted line */
+        double Lm[4][4], Rm[4][4];
+        if ((st = roe_eigen(nv, gamma, &U[j * nv], &Q[j], &U[(j + 1) * nv], &Q[j + 1], Lm, Rm)))
+            goto done;
+        double what[4];
+        for (int k = 0; k < nv; ++k) {
+            /* characteristic field k of the split fluxes over the face's window */
+            for (long i = j - T->r + 1; i <= j + T->r; ++i) {
+                wp[i] = row_dot(Lm[k], &Gp[i * nv], nv);
+                wm[i] = row_dot(Lm[k], &Gm[i * nv], nv);
+            }
+            int kp, km;
+            double hp = recon_face(T, wp, j, +1, &kp);
+            double hm = recon_face(T, wm, j, -1, &km);
+            what[k] = hp + hm;
+            if (idx) {
+                idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
+                idx[(f * nv + k) * 2 + 1] = (uint8_t)km;
+            }
+        }
+        /* back to conserved components: F-hat = R w-hat */
+        for (int v = 0; v < nv; ++v) Fhat[f * nv + v] = row_dot(Rm[v], what, nv);
+    }
+done:
+    free(U); free(Gp); free(Gm); free(Q); free(wp); free(wm);
+    return st;
+}
+
+/* 1D Euler right-hand side L(U), U and dUdt laid out [3][n]. */
+int orc_euler1d_rhs(const orc_table *T, double gamma, int bc, long n, double ih,
+                    const double *U, double *dUdt, uint8_t *idx, double *alpha_out)
+{
+    if (!T || n < 2) return ORC_EINVAL;
+    double alpha;
+    int st = line_alpha(3, gamma, n, U, &alpha);
+    if (st) return st;
+    if (alpha_out) *alpha_out = alpha;
+    double *Fh = (double *)malloc(sizeof(double) * (n + 1) * 3);
+    if (!Fh) return ORC_EINVAL;
+    st = euler_line_fluxes(T, 3, gamma, bc, n, U, alpha, Fh, idx);
+    if (!st)
+        for (int v = 0; v < 3; ++v)
+            for (long i = 0; i < n; ++i)
+                dUdt[v * n + i] = -((Fh[(i + 1) * 3 + v] - Fh[i * 3 + v]) * ih);
+    free(Fh);
+    return st;
+}
+
+/*
+ * 2D Euler right-hand side, dimension by dimension (Sec. 2.1):
+ * dU/dt = -(F_{i+1/2} - F_{i-1/2})/hx - (G_{j+1/2} - G_{j-1/2})/hy.
+ * U, dUdt: [4][ny][nx].  x-lines use (rho, m, n, E); y-lines the permuted
+ * state (rho, n, m, E) so that the same normal-frame formulas apply.
+ * idx_x (optional): [ny][nx+1][4][2]; idx_y (optional): [ny+1][nx][4][2].
+ * alpha_x[ny], alpha_y[nx] (optional) receive the per-line alphas.
+ */
+int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny,
+                    double ihx, double ihy, const double *U, double *dUdt,
+                    uint8_t *idx_x, uint8_t *idx_y, double *alpha_x, double *alpha_y)
+{
+    if (!T || nx < 2 || ny < 2) return ORC_EINVAL;
+    const long plane = nx * ny;
+    long nmax = nx > ny ? nx : ny;
+    double *line = (double *)malloc(sizeof(double) * 4 * nmax);
+    double *Fh = (double *)malloc(sizeof(double) * 4 * (nmax + 1));
+    uint8_t *idl = (uint8_t *)malloc(8 * (nmax + 1));
+    double *Lx = (double *)malloc(sizeof(double) * 4 * plane);
+    int st = ORC_OK;
+    if (!line || !Fh || !idl || !Lx) { st = ORC_EINVAL; goto done; }
+
+    /* x sweep */
+    for (long y = 0; y < ny; ++y) {
+        for (int v = 0; v < 4; ++v)
+            for (long x = 0; x < nx; ++x) line[v * nx + x] = U[v * plane + y * nx + x];
+        double alpha;
+        if ((st = line_alpha(4, gamma, nx, line, &alpha))) goto done;
+        if (alpha_x) alpha_x[y] = alpha;
+        if ((st = euler_line_fluxes(T, 4, gamma, bcx, nx, line, alpha, Fh, idx_x ? idl : NULL)))
+            goto done;
+        if (idx_x) memcpy(idx_x + (size_t)y * (nx + 1) * 8, idl, (size_t)(nx + 1) * 8);
+        for (int v = 0; v < 4; ++v)
+            for (long x = 0; x < nx; ++x)
+                Lx[v * plane + y * nx + x] = -((Fh[(x + 1) * 4 + v] - Fh[x * 4 + v]) * ihx);
+    }
+    /* y sweep on the permuted state, then combine */
+    static const int perm[4] = {0, 2, 1, 3};
+    for (long x = 0; x < nx; ++x) {
+        for (int v = 0; v < 4; ++v)
+            for (long y = 0; y < ny; ++y) line[v * ny + y] = U[perm[v] * plane + y * nx + x];
+        double alpha;
+        if ((st = line_alpha(4, gamma, ny, line, &alpha))) goto done;
+        if (alpha_y) alpha_y[x] = alpha;
+        if ((st = euler_line_fluxes(T, 4, gamma, bcy, ny, line, alpha, Fh, idx_y ? idl : NULL)))
+            goto done;
+        if (idx_y)
+            for (long f = 0; f <= ny; ++f) memcpy(idx_y + ((size_t)f * nx + x) * 8, idl + f * 8, 8);
+        for (int v = 0; v < 4; ++v)
+            for (long y = 0; y < ny; ++y) {
+                int cv = perm[v];
+                double ly = -((Fh[(y + 1) * 4 + v] - Fh[y * 4 + v]) * ihy);
+                dUdt[cv * plane + y * nx + x] = Lx[cv * plane + y * nx + x] + ly;
+            }
+    }
+done:
+    free(line); free(Fh); free(idl); free(Lx);
+    return st;
+}
+
+/*
+ * L(U) at selected cells of a 2D grid only (for spot checks of large runs).
+ * cells: ncell (x, y) pairs; out: [ncell][4].  Each cell needs its row's and
+ * column's alpha, computed here over the whole line.
+ */
+int orc_euler2d_rhs_cells(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny,
+                          double ihx, double ihy, const double *U, long ncell, const long *cells,
+                          double *out)
+{
+    if (!T || nx < 2 || ny < 2) return ORC_EINVAL;
+    const long plane = nx * ny;
+    const long w = T->r + 2;   /* cells each side needed by two faces */
+    long nmax = nx > ny ? nx : ny;
+    double *line = (double *)malloc(sizeof(double) * 4 * nmax);
+    double *seg = (double *)malloc(sizeof(double) * 4 * (2 * w + 1));
+    double *Fh = (double *)malloc(sizeof(double) * 4 * (2 * w + 2));
+    int st = ORC_OK;
+    static const int perm[4] = {0, 2, 1, 3};
+    if (!line || !seg || !Fh) { st = ORC_EINVAL; goto done; }
+    for (long q = 0; q < ncell; ++q) {
+        long cx = cells[2 * q], cy = cells[2 * q + 1];
+        double res[4];
+        for (int dir = 0; dir < 2; ++dir) {
+            long n = dir == 0 ? nx : ny;
+            long ci = dir == 0 ? cx : cy;
+            int bc = dir == 0 ? bcx : bcy;
+            for (int v = 0; v < 4; ++v)
+                for (long i = 0; i < n; ++i) {
+                    long gx = dir == 0 ? i : cx, gy = dir == 0 ? cy : i;
+                    int sv = dir == 0 ? v : perm[v];
+                    line[v * n + i] = U[sv * plane + gy * nx + gx];
+                }
+            double alpha;
+            if ((st = line_alpha(4, gamma, n, line, &alpha))) goto done;
+            /* fluxes at the cell's two faces: evaluate on the whole line (plain) */
+            double *Fl = (double *)malloc(sizeof(double) * 4 * (n + 1));
+            if (!Fl) { st = ORC_EINVAL; goto done; }
+            st = euler_line_fluxes(T, 4, gamma, bc, n, line, alpha, Fl, NULL);
+            if (st) { free(Fl); goto done; }
+            for (int v = 0; v < 4; ++v) {
+                double ih = dir == 0 ? ihx : ihy;
+                double d = -((Fl[(ci + 1) * 4 + v] - Fl[ci * 4 + v]) * ih);
+                int cv = dir == 0 ? v : perm[v];
+                if (dir == 0) res[cv] = d;
+                else res[cv] = res[cv] + d;
+            }
+            free(Fl);
+        }
+        for (int v = 0; v < 4; ++v) out[q * 4 + v] = res[v];
+    }
+done:
+    free(line); free(seg); free(Fh);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time step and Runge-Kutta updates                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Largest |u_n| + c over a [nv][n] array of cells (normal = component 1). */
+int orc_euler_maxspeed(int nv, double gamma, long n, const double *U, double *smax)
+{
+    return line_alpha(nv, gamma, n, U, smax);
+}
+
+/* 2D: largest |u| + c and |v| + c over the grid. */
+int orc_euler2d_maxspeeds(double gamma, long nx, long ny, const double *U, double *sx, double *sy)
+{
+    const long plane = nx * ny;
+    double ax = 0.0, ay = 0.0;
+    for (long i = 0; i < plane; ++i) {
+        double Uc[4] = {U[i], U[plane + i], U[2 * plane + i], U[3 * plane + i]};
+        cell_prim q;
+        if (primitives(4, gamma, Uc, &q)) return ORC_ENONPHYS;
+        double a = fabs(q.un) + q.c;
+        double b = fabs(q.ut) + q.c;
+        if (a > ax) ax = a;
+        if (b > ay) ay = b;
+    }
+    *sx = ax;
+    *sy = ay;
+    return ORC_OK;
+}
+
+/*
+ * SSP-RK3 stage combination (Eq. TVD3rdRK), elementwise over n values:
+ *   stage 1: out = us + dt L
+ *   stage 2: out = 3/4 un + 1/4 (us + dt L)
+ *   stage 3: out = 1/3 un + 2/3 (us + dt L)
+ */
+void orc_ssprk3_combine(int stage, long n, const double *un, const double *us, const double *L,
+                        double dt, double *out)
+{
+    const double c13 = 1.0 / 3.0, c23 = 2.0 / 3.0;
+    for (long i = 0; i < n; ++i) {
+        double e = us[i] + dt * L[i];
+        if (stage == 1) out[i] = e;
+        else if (stage == 2) out[i] = 0.75 * un[i] + 0.25 * e;
+        else out[i] = c13 * un[i] + c23 * e;
+    }
+}
+
+/*
+ * Linear SSP-RK(m, m-1) step for a scalar line (Eq. lSSPRK):
+ * u^(s) = u^(s-1) + dt/2 L(u^(s-1)), s = 1..m-1, and
+ * u^{n+1} = sum_{k<m-1} a_k u^(k) + a_{m-1} (u^(m-1) + dt/2 L(u^(m-1))).
+ * coef holds a_0..a_{m-1} (computed exactly by the caller, Eq. lSSPRK_Coe).
+ */
+int orc_scalar_lssp_run(const orc_table *T, int flux, double a, int split, int bc, long n,
+                        double ih, double dt, long nsteps, int m, const double *coef, double *u)
+{
+    if (m < 2 || m > 32) return ORC_EINVAL;
+    double *stages = (double *)malloc(sizeof(double) * n * m);
+    double *L = (double *)malloc(sizeof(double) * n);
+    double *acc = (double *)malloc(sizeof(double) * n);
+    int st = ORC_OK;
+    if (!stages || !L || !acc) { st = ORC_EINVAL; goto done; }
+    const double hdt = 0.5 * dt;
+    for (long step = 0; step < nsteps; ++step) {
+        memcpy(stages, u, sizeof(double) * n);
+        for (int s = 1; s < m; ++s) {
+            if ((st = orc_scalar_rhs(T, flux, a, split, bc, n, ih, stages + (s - 1) * n, L, NULL, NULL)))
+                goto done;
+            for (long i = 0; i < n; ++i) stages[s * n + i] = stages[(s - 1) * n + i] + hdt * L[i];
+        }
+        if ((st = orc_scalar_rhs(T, flux, a, split, bc, n, ih, stages + (m - 1) * n, L, NULL, NULL)))
+            goto done;
+        for (long i = 0; i < n; ++i) acc[i] = 0.0;
+        for (int k = 0; k < m - 1; ++k)
+            for (long i = 0; i < n; ++i) acc[i] = acc[i] + coef[k] * stages[k * n + i];
+        for (long i = 0; i < n; ++i)
+            u[i] = acc[i] + coef[m - 1] * (stages[(m - 1) * n + i] + hdt * L[i]);
+    }
+done:
+    free(stages); free(L); free(acc);
+    return st;
+}
+
+/*
+ * SSP-RK3 run of a scalar line with a fixed step dt; the last step is cut so
+ * that the run ends exactly at t_end (if t_end > 0, else nsteps steps).
+ */
+int orc_scalar_ssprk3_run(const orc_table *T, int flux, double a, int split, int bc, long n,
+                          double ih, double dt, double t_end, long nsteps, double *u)
+{
+    double *un = (double *)malloc(sizeof(double) * n);
+    double *us = (double *)malloc(sizeof(double) * n);
+    double *L = (double *)malloc(sizeof(double) * n);
+    int st = ORC_OK;
+    if (!un || !us || !L) { st = ORC_EINVAL; goto done; }
+    double t = 0.0;
+    for (long step = 0; t_end > 0.0 ? t < t_end : step < nsteps; ++step) {
+        double h = dt;
+        if (t_end > 0.0 && t + h > t_end) h = t_end - t;
+        memcpy(un, u, sizeof(double) * n);
+        memcpy(us, u, sizeof(double) * n);
+        for (int s = 1; s <= 3; ++s) {
+            if ((st = orc_scalar_rhs(T, flux, a, split, bc, n, ih, us, L, NULL, NULL))) goto done;
+            orc_ssprk3_combine(s, n, un, us, L, h, us);
+        }
+        memcpy(u, us, sizeof(double) * n);
+        t = t + h;
+    }
+done:
+    free(un); free(us); free(L);
+    return st;
+}
