@@ -14,7 +14,9 @@
  *
  *   - dot products (IS, fluxes, projections): first term a plain product, then
  *     fma() terms, in ascending physical cell (or component) order;
- *   - IS0 second differences: (f_c - 2 f_{c-1}) + f_{c-2}.
+ *   - IS0 second differences: (f_c - 2 f_{c-1}) + f_{c-2};
+ *   - one reciprocal per cell (1/rho) and per face (1/(sqrt(rho_L)+sqrt(rho_R)))
+ *     multiplies instead of repeated divisions.
  *
  * Method steps and where the paper states them:
  *   global Lax-Friedrichs splitting ............. Sec. 2.1, Eq. (LF_Flux_Split)
@@ -265,16 +267,17 @@ typedef struct {
 static int primitives(int nv, double gamma, const double *U, cell_prim *q)
 {
     double rho = U[0], mn = U[1], mt = nv == 4 ? U[2] : 0.0, E = U[nv - 1];
-    double un = mn / rho;
-    double ut = nv == 4 ? mt / rho : 0.0;
+    double ir = 1.0 / rho;
+    double un = mn * ir;
+    double ut = nv == 4 ? mt * ir : 0.0;
     double ke = nv == 4 ? 0.5 * (mn * un + mt * ut) : 0.5 * (mn * un);
     double p = (gamma - 1.0) * (E - ke);
     if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(mn)) return ORC_ENONPHYS;
     q->un = un;
     q->ut = ut;
     q->p = p;
-    q->c = sqrt((gamma * p) / rho);
-    q->H = (E + p) / rho;
+    q->c = sqrt((gamma * p) * ir);
+    q->H = (E + p) * ir;
     q->F[0] = mn;
     q->F[1] = mn * un + p;
     if (nv == 4) {
@@ -296,10 +299,10 @@ static int roe_eigen(int nv, double gamma, const double *UL, const cell_prim *qL
 {
     double sL = sqrt(UL[0]);
     double sR = sqrt(UR[0]);
-    double d = sL + sR;
-    double u = (sL * qL->un + sR * qR->un) / d;
-    double v = nv == 4 ? (sL * qL->ut + sR * qR->ut) / d : 0.0;
-    double H = (sL * qL->H + sR * qR->H) / d;
+    double id = 1.0 / (sL + sR);
+    double u = (sL * qL->un + sR * qR->un) * id;
+    double v = nv == 4 ? (sL * qL->ut + sR * qR->ut) * id : 0.0;
+    double H = (sL * qL->H + sR * qR->H) * id;
     double q2 = nv == 4 ? u * u + v * v : u * u;
     double c2 = (gamma - 1.0) * (H - 0.5 * q2);
     if (!(c2 > 0.0)) return ORC_ENONPHYS;
