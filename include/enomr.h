@@ -1,0 +1,161 @@
+/*
+ * enomr.h - C ABI of the MI355X (gfx950) ENO-MR library.
+ *
+ * ENO-MR is the finite-difference scheme of H. Shen, "An efficient class of
+ * increasingly high-order ENO schemes with multi-resolution" (arXiv 2311.15504):
+ * per-face flux reconstruction over nested candidate stencils (orders 5..17),
+ * global Lax-Friedrichs splitting, characteristic projection at Roe-averaged
+ * faces for the Euler equations, and SSP-RK3 time stepping.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All array arguments are DEVICE pointers on the context's device, owned by
+ *   the caller, FP64 unless stated, C-contiguous.  State arrays are laid out
+ *   [variable][y][x] (x fastest) and hold interior cells only; the library
+ *   applies the boundary conditions itself (periodic wrap or zero-gradient
+ *   copy) when it reads neighbours.
+ * - Every call is asynchronous and ordered on the context's HIP stream.  The
+ *   library keeps no pointer beyond the work it has enqueued.
+ * - Argument errors are returned at once (ENOMR_EINVAL, ENOMR_EORDER) and
+ *   nothing is enqueued.  HIP failures return ENOMR_EHIP.  A non-physical state
+ *   met on the device (rho <= 0, p <= 0, NaN) is latched in a device status word
+ *   and reported by enomr_check() as ENOMR_ENONPHYS.  The library never aborts
+ *   or prints; enomr_last_error() gives a message for the calling thread.
+ * - Stencil-index logs (uint8) hold, per face, per characteristic field and
+ *   per sign (+ then -), the position of the chosen stencil in the order's
+ *   candidate list (0 = the full stencil, see enomr_coefficients()).
+ */
+#ifndef ENOMR_H
+#define ENOMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ENOMR_OK = 0,
+    ENOMR_EINVAL = 1,    /* bad argument or shape                          */
+    ENOMR_EORDER = 2,    /* order not odd in 5..17                         */
+    ENOMR_ENOMEM = 3,    /* device allocation failed                       */
+    ENOMR_EHIP = 4,      /* a HIP runtime call failed                      */
+    ENOMR_ENONPHYS = 5,  /* non-physical state met on the device           */
+    ENOMR_ENODEV = 6     /* no usable gfx950 device                        */
+} enomr_status;
+
+enum { ENOMR_ADVECTION = 0, ENOMR_BURGERS = 1, ENOMR_EULER = 2 };
+enum { ENOMR_PERIODIC = 0, ENOMR_OUTFLOW = 1 };
+enum { ENOMR_SPLIT_NONE = 0, ENOMR_SPLIT_LF = 1 };
+
+/*
+ * A conservation law on a uniform grid (Sec. 2.1, Eq. 1DHCL; Sec. 4.3-4.4).
+ *   ndim     1 or 2.  1D states are [nvar][nx]; 2D states [nvar][ny][nx].
+ *   system   ENOMR_ADVECTION (u_t + a u_x = 0, nvar 1, ndim 1),
+ *            ENOMR_BURGERS (u_t + (u^2/2)_x = 0, nvar 1, ndim 1),
+ *            ENOMR_EULER (nvar 3 in 1D: rho, rho u, E; nvar 4 in 2D:
+ *            rho, rho u, rho v, E; ideal gas with ratio gamma).
+ *   nx, ny   interior nodes per axis (ny = 1 in 1D); at least 2r+1 each.
+ *   hx, hy   node spacing.
+ *   order    2r-1, odd in 5..17.
+ *   bc_x/y   ENOMR_PERIODIC or ENOMR_OUTFLOW (zero-gradient copy).
+ *   split    scalar laws only: ENOMR_SPLIT_LF (global Lax-Friedrichs,
+ *            Eq. LF_Flux_Split) or ENOMR_SPLIT_NONE (reconstruct f itself as
+ *            f^+, valid when f'(u) >= 0).  Euler always splits.
+ *   gamma    ratio of specific heats (Euler).
+ *   adv_speed  the constant a (advection).
+ */
+typedef struct {
+    int32_t ndim;
+    int32_t system;
+    int64_t nx, ny;
+    double hx, hy;
+    int32_t order;
+    int32_t bc_x, bc_y;
+    int32_t split;
+    double gamma;
+    double adv_speed;
+} enomr_problem;
+
+typedef struct enomr_ctx enomr_ctx;
+
+/* Context on `device` issuing work on `hip_stream` (a hipStream_t; NULL = the
+   null stream).  Uploads the coefficient tables.  *out owned by the caller
+   until enomr_destroy(). */
+enomr_status enomr_create(int device, void *hip_stream, enomr_ctx **out);
+enomr_status enomr_destroy(enomr_ctx *ctx);
+enomr_status enomr_set_stream(enomr_ctx *ctx, void *hip_stream);
+
+/* Message describing the last error returned on the calling thread. */
+const char *enomr_last_error(void);
+
+/*
+ * Host-only: the candidate list of `order` and its coefficients as the library
+ * uses them (Sec. 3.1 Eq. Candidates, Tables Flux_reconstruction1/2 and
+ * ISCoe1/2).  mn receives 2*ncand ints (m, n) for stencils S_{j-m}^{j+n} in
+ * selection order; a and b receive 17 doubles per candidate, entry l+m for
+ * offset l.  Any output pointer may be NULL.  Needs no GPU.
+ */
+enomr_status enomr_coefficients(int order, int32_t *ncand, int32_t *mn, double *a, double *b);
+
+/*
+ * Bare scalar ENO-MR reconstruction (Sec. 3.2, Steps 1-3.2) at n faces.
+ * f_with_halo: n + 2r - 1 values; face i lies between array entries i+r-1 and
+ * i+r.  sign = +1 reconstructs f^+ (centred on the left cell), -1 reconstructs
+ * f^- (the mirror image, centred on the right cell).  fhat: n values.
+ * idx (nullable): n bytes.
+ */
+enomr_status enomr_recon_faces(enomr_ctx *ctx, int order, int sign, int64_t n,
+                               const double *f_with_halo, double *fhat, uint8_t *idx);
+
+/* Bytes of device workspace that enomr_rhs/dt/ssprk3_step/advance need for
+   `prob`. */
+enomr_status enomr_workspace_size(const enomr_problem *prob, size_t *bytes);
+
+/*
+ * dU/dt = L(U) (Sec. 2.1 Eq. 1DWENOFD, dimension by dimension), with alpha of
+ * each line computed from U (Eq. LF_Flux_Split).  ws: workspace of
+ * enomr_workspace_size() bytes.  idx (nullable) receives the stencil log:
+ *   scalar 1D: [nx+1][2];  Euler 1D: [nx+1][3][2];
+ *   Euler 2D: x-faces [ny][nx+1][4][2] followed by y-faces [ny+1][nx][4][2].
+ * Face f of a line lies between cells f-1 and f (f = 0..n; for periodic lines
+ * faces 0 and n are the same face and carry the same values).
+ */
+enomr_status enomr_rhs(enomr_ctx *ctx, const enomr_problem *prob, const double *U,
+                       double *dUdt, uint8_t *idx, void *ws);
+
+/*
+ * Time step from the CFL rule, written to the device scalar *dt_dev:
+ *   1D: dt = cfl / (max(|u|+c) / hx), scalar laws use max|f'(u)|;
+ *   2D: dt = cfl / (max(|u|+c)/hx + max(|v|+c)/hy).
+ */
+enomr_status enomr_dt(enomr_ctx *ctx, const enomr_problem *prob, const double *U, double cfl,
+                      double *dt_dev, void *ws);
+
+/*
+ * One SSP-RK3 step (Sec. 2.3 Eq. TVD3rdRK) of U in place with the step size in
+ * the device scalar *dt_dev.  idx_log (nullable): the three stages' stencil
+ * logs back to back, each laid out as for enomr_rhs.
+ */
+enomr_status enomr_ssprk3_step(enomr_ctx *ctx, const enomr_problem *prob, double *U,
+                               const double *dt_dev, void *ws, uint8_t *idx_log);
+
+/*
+ * nsteps SSP-RK3 steps of U in place, each with dt from the CFL rule at the
+ * start of the step.  If t_end > 0 the run stops at t_end: the step that would
+ * pass it is shortened to end there and later steps do nothing.  dt_log
+ * (nullable, device, nsteps doubles) receives the step sizes used.
+ */
+enomr_status enomr_advance(enomr_ctx *ctx, const enomr_problem *prob, double *U, double cfl,
+                           int64_t nsteps, double t_end, void *ws, double *dt_log);
+
+/* Wait for the context's stream, then return and clear the device status
+   (ENOMR_OK or ENOMR_ENONPHYS). */
+enomr_status enomr_check(enomr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENOMR_H */

@@ -1,0 +1,217 @@
+"""Python binding of libenomr (the MI355X ENO-MR library, include/enomr.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libenomr.so.  PyTorch provides device memory and the stream; arrays are
+torch float64 CUDA tensors laid out [variable][y][x].  If the library is
+missing or cannot be loaded this module raises at first use: there is no CPU
+fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libenomr.so")
+
+ADVECTION, BURGERS, EULER = 0, 1, 2
+PERIODIC, OUTFLOW = 0, 1
+SPLIT_NONE, SPLIT_LF = 0, 1
+
+STATUS = {0: "ENOMR_OK", 1: "ENOMR_EINVAL", 2: "ENOMR_EORDER", 3: "ENOMR_ENOMEM", 4: "ENOMR_EHIP",
+          5: "ENOMR_ENONPHYS", 6: "ENOMR_ENODEV"}
+
+
+class EnomrError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    """Mirror of enomr_problem."""
+    _fields_ = [("ndim", ctypes.c_int32), ("system", ctypes.c_int32), ("nx", ctypes.c_int64),
+                ("ny", ctypes.c_int64), ("hx", ctypes.c_double), ("hy", ctypes.c_double),
+                ("order", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+                ("split", ctypes.c_int32), ("gamma", ctypes.c_double), ("adv_speed", ctypes.c_double)]
+
+    @classmethod
+    def scalar(cls, system, n, h, order, bc=PERIODIC, split=SPLIT_LF, adv_speed=1.0):
+        return cls(1, system, n, 1, h, 0.0, order, bc, PERIODIC, split, 0.0, adv_speed)
+
+    @classmethod
+    def euler1d(cls, n, h, order, bc=OUTFLOW, gamma=1.4):
+        return cls(1, EULER, n, 1, h, 0.0, order, bc, PERIODIC, SPLIT_LF, gamma, 0.0)
+
+    @classmethod
+    def euler2d(cls, nx, ny, hx, hy, order, bc_x=PERIODIC, bc_y=OUTFLOW, gamma=1.4):
+        return cls(2, EULER, nx, ny, hx, hy, order, bc_x, bc_y, SPLIT_LF, gamma, 0.0)
+
+    @property
+    def nvar(self):
+        if self.system != EULER:
+            return 1
+        return 4 if self.ndim == 2 else 3
+
+    @property
+    def state_shape(self):
+        if self.ndim == 2:
+            return (self.nvar, self.ny, self.nx)
+        return (self.nvar, self.nx)
+
+    def idx_bytes(self):
+        """Bytes of one stencil-index log (see enomr_rhs)."""
+        if self.system != EULER:
+            return (self.nx + 1) * 2
+        if self.ndim == 1:
+            return (self.nx + 1) * 6
+        return self.ny * (self.nx + 1) * 8 + (self.ny + 1) * self.nx * 8
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libenomr.so (built in-tree by build.py); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libenomr.so not built: run paper_2311_15504_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        st = ctypes.c_int
+        P = ctypes.POINTER(Problem)
+        sig = {
+            "enomr_create": ([ctypes.c_int, _vp, ctypes.POINTER(_vp)], st),
+            "enomr_destroy": ([_vp], st),
+            "enomr_set_stream": ([_vp, _vp], st),
+            "enomr_last_error": ([], ctypes.c_char_p),
+            "enomr_coefficients": ([ctypes.c_int, _vp, _vp, _vp, _vp], st),
+            "enomr_recon_faces": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _vp, _vp, _vp], st),
+            "enomr_workspace_size": ([P, ctypes.POINTER(ctypes.c_size_t)], st),
+            "enomr_rhs": ([_vp, P, _vp, _vp, _vp, _vp], st),
+            "enomr_dt": ([_vp, P, _vp, ctypes.c_double, _vp, _vp], st),
+            "enomr_ssprk3_step": ([_vp, P, _vp, _vp, _vp, _vp], st),
+            "enomr_advance": ([_vp, P, _vp, ctypes.c_double, ctypes.c_int64, ctypes.c_double, _vp, _vp], st),
+            "enomr_check": ([_vp], st),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _call(name, *args):
+    st = getattr(lib(), name)(*args)
+    if st != 0:
+        raise EnomrError(st, (lib().enomr_last_error() or b"").decode())
+    return st
+
+
+def coefficients(order):
+    """(mn, a, b) as the library uses them; host only, no GPU needed."""
+    import numpy as np
+    nc = ctypes.c_int32()
+    _call("enomr_coefficients", order, ctypes.cast(ctypes.byref(nc), _vp), None, None, None)
+    mn = np.zeros(2 * nc.value, dtype=np.int32)
+    a = np.zeros(nc.value * 17)
+    b = np.zeros(nc.value * 17)
+    _call("enomr_coefficients", order, ctypes.cast(ctypes.byref(nc), _vp), mn.ctypes.data, a.ctypes.data,
+          b.ctypes.data)
+    return mn.reshape(-1, 2), a.reshape(-1, 17), b.reshape(-1, 17)
+
+
+def workspace_size(prob):
+    n = ctypes.c_size_t()
+    _call("enomr_workspace_size", ctypes.byref(prob), ctypes.byref(n))
+    return n.value
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An enomr_ctx bound to a CUDA (HIP) device; calls follow torch's current stream."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _call("enomr_create", device, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(h))
+        self.handle = h
+        self._ws = {}
+
+    def close(self):
+        if self.handle:
+            lib().enomr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        _call("enomr_set_stream", self.handle, ctypes.c_void_p(s))
+
+    def workspace(self, prob):
+        key = bytes(prob)
+        if key not in self._ws:
+            self._ws[key] = self.torch.empty(workspace_size(prob), dtype=self.torch.uint8, device=self.device)
+        return self._ws[key]
+
+    def _check_state(self, prob, U):
+        t = self.torch
+        if U.dtype != t.float64 or not U.is_cuda or not U.is_contiguous() or tuple(U.shape) != prob.state_shape:
+            raise ValueError("state must be a contiguous float64 CUDA tensor of shape %s" % (prob.state_shape,))
+
+    # -- entry points -------------------------------------------------------
+
+    def recon_faces(self, order, sign, f_with_halo, with_idx=True):
+        t = self.torch
+        r = (order + 1) // 2
+        n = f_with_halo.numel() - (2 * r - 1)
+        fhat = t.empty(max(n, 0), dtype=t.float64, device=self.device)
+        idx = t.empty(max(n, 0), dtype=t.uint8, device=self.device) if with_idx else None
+        self._sync_stream()
+        _call("enomr_recon_faces", self.handle, order, sign, n, _ptr(f_with_halo), _ptr(fhat), _ptr(idx))
+        return fhat, idx
+
+    def rhs(self, prob, U, with_idx=False):
+        t = self.torch
+        self._check_state(prob, U)
+        out = t.empty_like(U)
+        idx = t.empty(prob.idx_bytes(), dtype=t.uint8, device=self.device) if with_idx else None
+        self._sync_stream()
+        _call("enomr_rhs", self.handle, ctypes.byref(prob), _ptr(U), _ptr(out), _ptr(idx), _ptr(self.workspace(prob)))
+        return (out, idx) if with_idx else out
+
+    def dt(self, prob, U, cfl):
+        t = self.torch
+        self._check_state(prob, U)
+        d = t.empty(1, dtype=t.float64, device=self.device)
+        self._sync_stream()
+        _call("enomr_dt", self.handle, ctypes.byref(prob), _ptr(U), cfl, _ptr(d), _ptr(self.workspace(prob)))
+        return d
+
+    def ssprk3_step(self, prob, U, dt_dev, idx_log=None):
+        self._check_state(prob, U)
+        self._sync_stream()
+        _call("enomr_ssprk3_step", self.handle, ctypes.byref(prob), _ptr(U), _ptr(dt_dev),
+              _ptr(self.workspace(prob)), _ptr(idx_log))
+
+    def advance(self, prob, U, cfl, nsteps, t_end=0.0, dt_log=None):
+        self._check_state(prob, U)
+        self._sync_stream()
+        _call("enomr_advance", self.handle, ctypes.byref(prob), _ptr(U), cfl, nsteps, t_end,
+              _ptr(self.workspace(prob)), _ptr(dt_log))
+
+    def check(self):
+        self._sync_stream()
+        _call("enomr_check", self.handle)

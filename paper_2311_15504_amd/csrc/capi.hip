@@ -1,0 +1,451 @@
+// Host side of the C ABI declared in include/enomr.h: argument checks,
+// workspace layout, kernel launches on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/enomr.h"
+#include "kernels.hpp"
+
+namespace enomr {
+__constant__ double c_a[kPool][kMaxW];
+__constant__ double c_b[kPool][kMaxW];
+}  // namespace enomr
+
+using namespace enomr;
+
+struct enomr_ctx {
+    int device;
+    hipStream_t stream;
+    unsigned* status;   // device word, latched non-physical flag
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+enomr_status fail(enomr_status st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(ENOMR_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+int nvar(const enomr_problem& p)
+{
+    if (p.system == ENOMR_EULER) return p.ndim == 2 ? 4 : 3;
+    return 1;
+}
+
+bool order_ok(int order) { return order >= 5 && order <= 17 && (order & 1); }
+
+enomr_status check_problem(const enomr_problem* p)
+{
+    if (!p) return fail(ENOMR_EINVAL, "problem is NULL");
+    if (!order_ok(p->order)) return fail(ENOMR_EORDER, "order must be odd in 5..17");
+    const int r = (p->order + 1) / 2;
+    if (p->ndim != 1 && p->ndim != 2) return fail(ENOMR_EINVAL, "ndim must be 1 or 2");
+    if (p->system != ENOMR_ADVECTION && p->system != ENOMR_BURGERS && p->system != ENOMR_EULER)
+        return fail(ENOMR_EINVAL, "unknown system");
+    if (p->system != ENOMR_EULER && p->ndim != 1) return fail(ENOMR_EINVAL, "scalar laws are 1D only");
+    if (p->nx < 2 * r + 1) return fail(ENOMR_EINVAL, "nx must be at least 2r+1");
+    if (p->ndim == 1 && p->ny != 1) return fail(ENOMR_EINVAL, "ny must be 1 for ndim = 1");
+    if (p->ndim == 2 && p->ny < 2 * r + 1) return fail(ENOMR_EINVAL, "ny must be at least 2r+1");
+    if (!(p->hx > 0.0) || (p->ndim == 2 && !(p->hy > 0.0))) return fail(ENOMR_EINVAL, "spacing must be > 0");
+    if ((p->bc_x != ENOMR_PERIODIC && p->bc_x != ENOMR_OUTFLOW) ||
+        (p->ndim == 2 && p->bc_y != ENOMR_PERIODIC && p->bc_y != ENOMR_OUTFLOW))
+        return fail(ENOMR_EINVAL, "unknown boundary condition");
+    if (p->system == ENOMR_EULER && !(p->gamma > 1.0)) return fail(ENOMR_EINVAL, "gamma must be > 1");
+    if (p->system != ENOMR_EULER && p->split != ENOMR_SPLIT_LF && p->split != ENOMR_SPLIT_NONE)
+        return fail(ENOMR_EINVAL, "unknown split");
+    if (p->nx > (1L << 31) || p->ny > (1L << 31)) return fail(ENOMR_EINVAL, "grid too large");
+    return ENOMR_OK;
+}
+
+// Workspace: two stage states, one operator buffer, per-line alphas and a
+// few device scalars.
+struct Layout {
+    size_t U1, U2, L, ax, ay, dt, t, active, total;
+};
+
+Layout layout(const enomr_problem& p)
+{
+    Layout w;
+    const size_t state = sizeof(double) * nvar(p) * (size_t)p.nx * (size_t)p.ny;
+    size_t off = 0;
+    w.U1 = off; off += align_up(state);
+    w.U2 = off; off += align_up(state);
+    w.L = off; off += p.ndim == 2 ? align_up(state) : 0;
+    w.ax = off; off += align_up(sizeof(double) * (size_t)p.ny);
+    w.ay = off; off += align_up(sizeof(double) * (size_t)(p.ndim == 2 ? p.nx : 1));
+    w.dt = off; off += 256;
+    w.t = off; off += 256;
+    w.active = off; off += 256;
+    w.total = off;
+    return w;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+unsigned blocks_for(long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+#define DISPATCH_R(order, ...)                      \
+    switch (((order) + 1) / 2) {                    \
+    case 3: { constexpr int R = 3; __VA_ARGS__; } break;  \
+    case 4: { constexpr int R = 4; __VA_ARGS__; } break;  \
+    case 5: { constexpr int R = 5; __VA_ARGS__; } break;  \
+    case 6: { constexpr int R = 6; __VA_ARGS__; } break;  \
+    case 7: { constexpr int R = 7; __VA_ARGS__; } break;  \
+    case 8: { constexpr int R = 8; __VA_ARGS__; } break;  \
+    case 9: { constexpr int R = 9; __VA_ARGS__; } break;  \
+    default: break;                                 \
+    }
+
+// Tile shapes (faces per line x lines per block).
+constexpr int kTF1 = 64;                  // 1D lines
+constexpr int kTFx = 64, kTLx = 4;        // 2D x sweep
+constexpr int kTFy = 32, kTLy = 8;        // 2D y sweep
+
+// Alphas of every line of `Us` into ws (zeroed first).
+enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* Us, void* ws,
+                          const int* active)
+{
+    const Layout w = layout(p);
+    double* ax = at<double>(ws, w.ax);
+    double* ay = at<double>(ws, w.ay);
+    const long nax = p.ny, nay = p.ndim == 2 ? p.nx : 1;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(nax, 256)), dim3(256), 0, ctx->stream, ax, nax, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(nay, 256)), dim3(256), 0, ctx->stream, ay, nay, 0.0);
+    if (p.system == ENOMR_EULER) {
+        dim3 grid(blocks_for(p.nx, 64), blocks_for(p.ny, 32));
+        if (p.ndim == 2)
+            hipLaunchKernelGGL(k_alpha_euler<4>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
+                               p.gamma, ax, ay, ctx->status, active);
+        else
+            hipLaunchKernelGGL(k_alpha_euler<3>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
+                               p.gamma, ax, ay, ctx->status, active);
+    } else {
+        const unsigned nb = blocks_for(p.nx, 256) < 64 ? blocks_for(p.nx, 256) : 64;
+        hipLaunchKernelGGL(k_alpha_scalar, dim3(nb), dim3(256), 0, ctx->stream, Us, (long)p.nx,
+                           p.system == ENOMR_ADVECTION ? SYS_ADVECTION : SYS_BURGERS, p.adv_speed, ax, active);
+    }
+    HIP_TRY(hipGetLastError());
+    return ENOMR_OK;
+}
+
+// The operator L(Us) and its use: stage 0 stores L into so.out, stages 1..3
+// combine the SSP-RK3 stage.  Requires the alphas of Us in ws.
+enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const double* Us, StageOut so,
+                             uint8_t* idx, void* ws, const int* active)
+{
+    const Layout w = layout(p);
+    const double* ax = at<double>(ws, w.ax);
+    const double* ay = at<double>(ws, w.ay);
+    if (p.system != ENOMR_EULER) {
+        const int flux = p.system == ENOMR_ADVECTION ? SYS_ADVECTION : SYS_BURGERS;
+        const int split = p.split == ENOMR_SPLIT_LF ? 1 : 0;
+        DISPATCH_R(p.order,
+                   hipLaunchKernelGGL((k_scalar_sweep<R, kTF1>), dim3(blocks_for(p.nx, kTF1 - 1)), dim3(kTF1), 0,
+                                      ctx->stream, Us, (long)p.nx, 1.0 / p.hx, flux, p.adv_speed, split, p.bc_x,
+                                      ax, so, idx, active));
+        HIP_TRY(hipGetLastError());
+        return ENOMR_OK;
+    }
+    SweepIn in;
+    in.Us = Us;
+    in.status = ctx->status;
+    in.active = active;
+    in.nx = p.nx;
+    in.ny = p.ny;
+    in.gamma = p.gamma;
+    if (p.ndim == 1) {
+        in.alpha = ax;
+        in.idx = idx;
+        in.ih = 1.0 / p.hx;
+        in.bc = p.bc_x;
+        DISPATCH_R(p.order,
+                   hipLaunchKernelGGL((k_euler_sweep<3, R, 0, kTF1, 1>), dim3(blocks_for(p.nx, kTF1 - 1), 1),
+                                      dim3(kTF1), 0, ctx->stream, in, so));
+        HIP_TRY(hipGetLastError());
+        return ENOMR_OK;
+    }
+    // 2D: x sweep stores L_x into the workspace, the y sweep adds L_y and
+    // either stores the sum or combines the RK stage.
+    double* Lx = at<double>(ws, w.L);
+    StageOut sx;
+    sx.Un = nullptr;
+    sx.Lprev = nullptr;
+    sx.out = Lx;
+    sx.dt = nullptr;
+    sx.stage = 0;
+    in.alpha = ax;
+    in.idx = idx;
+    in.ih = 1.0 / p.hx;
+    in.bc = p.bc_x;
+    DISPATCH_R(p.order,
+               hipLaunchKernelGGL((k_euler_sweep<4, R, 0, kTFx, kTLx>),
+                                  dim3(blocks_for(p.nx, kTFx - 1), blocks_for(p.ny, kTLx)), dim3(kTFx * kTLx), 0,
+                                  ctx->stream, in, sx));
+    HIP_TRY(hipGetLastError());
+    in.alpha = ay;
+    in.idx = idx ? idx + (size_t)p.ny * (p.nx + 1) * 8 : nullptr;
+    in.ih = 1.0 / p.hy;
+    in.bc = p.bc_y;
+    so.Lprev = Lx;
+    DISPATCH_R(p.order,
+               hipLaunchKernelGGL((k_euler_sweep<4, R, 1, kTFy, kTLy>),
+                                  dim3(blocks_for(p.ny, kTFy - 1), blocks_for(p.nx, kTLy)), dim3(kTFy * kTLy), 0,
+                                  ctx->stream, in, so));
+    HIP_TRY(hipGetLastError());
+    return ENOMR_OK;
+}
+
+size_t idx_bytes(const enomr_problem& p)
+{
+    if (p.system != ENOMR_EULER) return (size_t)(p.nx + 1) * 2;
+    if (p.ndim == 1) return (size_t)(p.nx + 1) * 6;
+    return (size_t)p.ny * (p.nx + 1) * 8 + (size_t)(p.ny + 1) * p.nx * 8;
+}
+
+enomr_status launch_dt(enomr_ctx* ctx, const enomr_problem& p, double cfl, void* ws, double* dt, double t_end,
+                       double* dt_log, long step)
+{
+    const Layout w = layout(p);
+    const long nax = p.system == ENOMR_EULER ? p.ny : 1;
+    const long nay = p.ndim == 2 ? p.nx : 0;
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, at<double>(ws, w.ax), nax, at<double>(ws, w.ay),
+                       nay, cfl, 1.0 / p.hx, p.ndim == 2 ? 1.0 / p.hy : 0.0, t_end, dt, at<double>(ws, w.t),
+                       at<int>(ws, w.active), dt_log, step);
+    HIP_TRY(hipGetLastError());
+    return ENOMR_OK;
+}
+
+// One SSP-RK3 step of U in place.
+enomr_status rk3_step(enomr_ctx* ctx, const enomr_problem& p, double* U, const double* dt, void* ws,
+                      uint8_t* idx_log, const int* active, bool alpha_ready)
+{
+    const Layout w = layout(p);
+    double* U1 = at<double>(ws, w.U1);
+    double* U2 = at<double>(ws, w.U2);
+    const double* stage_in[3] = {U, U1, U2};
+    double* stage_out[3] = {U1, U2, U};
+    const size_t ib = idx_bytes(p);
+    for (int s = 0; s < 3; ++s) {
+        if (!(s == 0 && alpha_ready)) {
+            enomr_status st = launch_alpha(ctx, p, stage_in[s], ws, active);
+            if (st) return st;
+        }
+        StageOut so;
+        so.Un = U;
+        so.Lprev = nullptr;
+        so.out = stage_out[s];
+        so.dt = dt;
+        so.stage = s + 1;
+        enomr_status st = launch_operator(ctx, p, stage_in[s], so, idx_log ? idx_log + s * ib : nullptr, ws, active);
+        if (st) return st;
+    }
+    return ENOMR_OK;
+}
+
+enomr_status check_ctx(enomr_ctx* ctx)
+{
+    if (!ctx) return fail(ENOMR_EINVAL, "context is NULL");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(ENOMR_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    return ENOMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* enomr_last_error(void) { return g_err.c_str(); }
+
+enomr_status enomr_coefficients(int order, int32_t* ncand, int32_t* mn, double* a, double* b)
+{
+    if (!order_ok(order)) return fail(ENOMR_EORDER, "order must be odd in 5..17");
+    static double ta[kPool][kMaxW], tb[kPool][kMaxW];
+    static bool ready = generate_tables(ta, tb);
+    (void)ready;
+    const int R = (order + 1) / 2;
+    const int nc = n_cands(R);
+    if (ncand) *ncand = nc;
+    for (int c = 0; c < nc; ++c) {
+        const int P = cand_pool(R, c);
+        if (mn) {
+            mn[2 * c] = pool_mn(P, 0);
+            mn[2 * c + 1] = pool_mn(P, 1);
+        }
+        for (int l = 0; l < kMaxW; ++l) {
+            if (a) a[c * kMaxW + l] = ta[P][l];
+            if (b) b[c * kMaxW + l] = tb[P][l];
+        }
+    }
+    return ENOMR_OK;
+}
+
+enomr_status enomr_create(int device, void* hip_stream, enomr_ctx** out)
+{
+    if (!out) return fail(ENOMR_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(ENOMR_ENODEV, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(ENOMR_ENODEV, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+    static double ta[kPool][kMaxW], tb[kPool][kMaxW];
+    static bool ready = generate_tables(ta, tb);
+    (void)ready;
+    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_a), ta, sizeof(ta)));
+    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_b), tb, sizeof(tb)));
+    enomr_ctx* c = new enomr_ctx;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->status = nullptr;
+    hipError_t e = hipMalloc(&c->status, sizeof(unsigned));
+    if (e != hipSuccess) {
+        delete c;
+        return fail(ENOMR_ENOMEM, "cannot allocate the status word");
+    }
+    e = hipMemset(c->status, 0, sizeof(unsigned));
+    if (e != hipSuccess) {
+        (void)hipFree(c->status);
+        delete c;
+        return fail(ENOMR_EHIP, "cannot clear the status word");
+    }
+    *out = c;
+    return ENOMR_OK;
+}
+
+enomr_status enomr_destroy(enomr_ctx* ctx)
+{
+    if (!ctx) return ENOMR_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->status);
+    delete ctx;
+    return ENOMR_OK;
+}
+
+enomr_status enomr_set_stream(enomr_ctx* ctx, void* hip_stream)
+{
+    if (!ctx) return fail(ENOMR_EINVAL, "context is NULL");
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return ENOMR_OK;
+}
+
+enomr_status enomr_recon_faces(enomr_ctx* ctx, int order, int sign, int64_t n, const double* f_with_halo,
+                               double* fhat, uint8_t* idx)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    if (!order_ok(order)) return fail(ENOMR_EORDER, "order must be odd in 5..17");
+    if (sign != 1 && sign != -1) return fail(ENOMR_EINVAL, "sign must be +1 or -1");
+    if (n < 0 || (n > 0 && (!f_with_halo || !fhat))) return fail(ENOMR_EINVAL, "bad arrays");
+    if (n == 0) return ENOMR_OK;
+    const unsigned nb = blocks_for(n, 256);
+    if (sign > 0) {
+        DISPATCH_R(order, hipLaunchKernelGGL((k_recon_faces<R, 1>), dim3(nb), dim3(256), 0, ctx->stream,
+                                             f_with_halo, (long)n, fhat, idx));
+    } else {
+        DISPATCH_R(order, hipLaunchKernelGGL((k_recon_faces<R, -1>), dim3(nb), dim3(256), 0, ctx->stream,
+                                             f_with_halo, (long)n, fhat, idx));
+    }
+    HIP_TRY(hipGetLastError());
+    return ENOMR_OK;
+}
+
+enomr_status enomr_workspace_size(const enomr_problem* prob, size_t* bytes)
+{
+    if (enomr_status st = check_problem(prob)) return st;
+    if (!bytes) return fail(ENOMR_EINVAL, "bytes is NULL");
+    *bytes = layout(*prob).total;
+    return ENOMR_OK;
+}
+
+enomr_status enomr_rhs(enomr_ctx* ctx, const enomr_problem* prob, const double* U, double* dUdt, uint8_t* idx,
+                       void* ws)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    if (enomr_status st = check_problem(prob)) return st;
+    if (!U || !dUdt || !ws) return fail(ENOMR_EINVAL, "NULL array");
+    if (enomr_status st = launch_alpha(ctx, *prob, U, ws, nullptr)) return st;
+    StageOut so;
+    so.Un = nullptr;
+    so.Lprev = nullptr;
+    so.out = dUdt;
+    so.dt = nullptr;
+    so.stage = 0;
+    return launch_operator(ctx, *prob, U, so, idx, ws, nullptr);
+}
+
+enomr_status enomr_dt(enomr_ctx* ctx, const enomr_problem* prob, const double* U, double cfl, double* dt_dev,
+                      void* ws)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    if (enomr_status st = check_problem(prob)) return st;
+    if (!U || !dt_dev || !ws) return fail(ENOMR_EINVAL, "NULL array");
+    if (!(cfl > 0.0)) return fail(ENOMR_EINVAL, "cfl must be > 0");
+    if (enomr_status st = launch_alpha(ctx, *prob, U, ws, nullptr)) return st;
+    return launch_dt(ctx, *prob, cfl, ws, dt_dev, 0.0, nullptr, 0);
+}
+
+enomr_status enomr_ssprk3_step(enomr_ctx* ctx, const enomr_problem* prob, double* U, const double* dt_dev,
+                               void* ws, uint8_t* idx_log)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    if (enomr_status st = check_problem(prob)) return st;
+    if (!U || !dt_dev || !ws) return fail(ENOMR_EINVAL, "NULL array");
+    return rk3_step(ctx, *prob, U, dt_dev, ws, idx_log, nullptr, false);
+}
+
+enomr_status enomr_advance(enomr_ctx* ctx, const enomr_problem* prob, double* U, double cfl, int64_t nsteps,
+                           double t_end, void* ws, double* dt_log)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    if (enomr_status st = check_problem(prob)) return st;
+    if (!U || !ws) return fail(ENOMR_EINVAL, "NULL array");
+    if (!(cfl > 0.0) || nsteps < 0) return fail(ENOMR_EINVAL, "bad cfl or nsteps");
+    const Layout w = layout(*prob);
+    double* dt = at<double>(ws, w.dt);
+    int* active = at<int>(ws, w.active);
+    double* t = at<double>(ws, w.t);
+    // t = 0, active = 1 (fill kernels, so a captured sequence replays cleanly)
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, ctx->stream, t, 1L, 0.0);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, ctx->stream, active, 1);
+    HIP_TRY(hipGetLastError());
+    const int* act = t_end > 0.0 ? active : nullptr;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (enomr_status st = launch_alpha(ctx, *prob, U, ws, act)) return st;
+        if (enomr_status st = launch_dt(ctx, *prob, cfl, ws, dt, t_end, dt_log, (long)s)) return st;
+        if (enomr_status st = rk3_step(ctx, *prob, U, dt, ws, nullptr, act, true)) return st;
+    }
+    return ENOMR_OK;
+}
+
+enomr_status enomr_check(enomr_ctx* ctx)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    unsigned h = 0;
+    HIP_TRY(hipMemcpy(&h, ctx->status, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (h) {
+        HIP_TRY(hipMemset(ctx->status, 0, sizeof(unsigned)));
+        return fail(ENOMR_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN) met on the device");
+    }
+    return ENOMR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Device-side ENO-MR stencil selection (arXiv 2311.15504, Sec. 3.2).
+//
+// A reconstruction window w[0 .. 2R-2] holds 2R-1 values in ascending cell
+// order with the centre cell at w[R-1].  For sign S = +1 the centre is the
+// left cell j of face j+1/2 and stencil offset l is w[R-1+l]; for S = -1
+// (f^-, the mirror image about x_{j+1/2}) the centre is j+1 and offset l is
+// w[R-1-l].  Every dot product runs over ascending cells: a plain product for
+// the first term, then fma.  The host compiles this with -ffp-contract=off, so
+// no other operation is fused; the CPU oracle evaluates the same expressions
+// in the same order, which makes the stencil choices bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tables.hpp"
+
+namespace enomr {
+
+// a_l and b_l of every pool stencil, entry l+m (filled at context creation).
+extern __constant__ double c_a[kPool][kMaxW];
+extern __constant__ double c_b[kPool][kMaxW];
+
+// Coefficient index of window entry i for stencil (m, n) and sign S.
+template <int R, int S, int m>
+__device__ constexpr int coef_index(int i)
+{
+    return S > 0 ? i - (R - 1) + m : (R - 1 - i) + m;
+}
+
+// sum_l coef[l+m] w(l) over stencil pool entry P, ascending cells.
+template <int R, int S, int P>
+__device__ __forceinline__ double sdot(const double* coef, const double (&w)[2 * R - 1])
+{
+    constexpr int m = pool_mn(P, 0), n = pool_mn(P, 1);
+    constexpr int lo = S > 0 ? R - 1 - m : R - 1 - n;
+    constexpr int hi = S > 0 ? R - 1 + n : R - 1 + m;
+    double acc = coef[coef_index<R, S, m>(lo)] * w[lo];
+#pragma unroll
+    for (int i = lo + 1; i <= hi; ++i) acc = fma(coef[coef_index<R, S, m>(i)], w[i], acc);
+    return acc;
+}
+
+// Step 1: IS0 = min(IS_L, IS_R), Eq. (Baseline_IS).
+template <int R, int S>
+__device__ __forceinline__ double baseline_is(const double (&w)[2 * R - 1])
+{
+    const double f0 = w[R - 1];
+    const double fm1 = S > 0 ? w[R - 2] : w[R];
+    const double fm2 = S > 0 ? w[R - 3] : w[R + 1];
+    const double fp1 = S > 0 ? w[R] : w[R - 2];
+    const double fp2 = S > 0 ? w[R + 1] : w[R - 3];
+    const double isl = fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2));
+    const double isr = fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2));
+    return fmin(isl, isr);
+}
+
+// Step 3.2: f_c + minmod(f_{c+1} - f_c, f_c - f_{c-1}) / 2 in the sign's frame.
+template <int R, int S>
+__device__ __forceinline__ double minmod_flux(const double (&w)[2 * R - 1], int& idx)
+{
+    constexpr int NC = n_cands(R);
+    const double f0 = w[R - 1];
+    const double fp1 = S > 0 ? w[R] : w[R - 2];
+    const double fm1 = S > 0 ? w[R - 2] : w[R];
+    const double da = fp1 - f0;
+    const double db = f0 - fm1;
+    double mm;
+    if (da * db > 0.0) {
+        if (fabs(da) <= fabs(db)) { mm = da; idx = NC - 3; }   // S_j^{j+1}
+        else { mm = db; idx = NC - 2; }                          // S_{j-1}^{j}
+    } else {
+        mm = 0.0; idx = NC - 1;                                   // S_j^{j}
+    }
+    return f0 + 0.5 * mm;
+}
+
+// Steps 3.1/3.2 from candidate C on: the first candidate (list order) with
+// m, n >= 1 and IS < IS0 gives the flux, otherwise minmod.
+template <int R, int S, int C>
+__device__ __forceinline__ double select_from(const double (&w)[2 * R - 1], double is0, int& idx)
+{
+    if constexpr (C < n_cands(R)) {
+        constexpr int P = cand_pool(R, C);
+        constexpr int m = pool_mn(P, 0), n = pool_mn(P, 1);
+        if constexpr (m >= 1 && n >= 1) {
+            const double is = fabs(sdot<R, S, P>(c_b[P], w));
+            if (is < is0) {
+                idx = C;
+                return sdot<R, S, P>(c_a[P], w);
+            }
+        }
+        return select_from<R, S, C + 1>(w, is0, idx);
+    } else {
+        return minmod_flux<R, S>(w, idx);
+    }
+}
+
+// The whole scalar reconstruction (Steps 1-3.2) of one window.
+template <int R, int S>
+__device__ __forceinline__ double recon(const double (&w)[2 * R - 1], int& idx)
+{
+    const double is0 = baseline_is<R, S>(w);
+    return select_from<R, S, 0>(w, is0, idx);
+}
+
+}  // namespace enomr

@@ -1,0 +1,614 @@
+// HIP kernels of the ENO-MR hot path for gfx950 (arXiv 2311.15504).
+//
+// Data layout: FP64 planes [variable][y][x], x fastest; a 1D problem is one
+// row.  A "line" is a row (x-sweep) or a column (y-sweep).  Sweep kernels work
+// on tiles of TL lines x TF faces; each tile stages its cells plus r halo
+// cells per side in LDS (structure of arrays, so that the lanes of a
+// wavefront read consecutive doubles), with boundary conditions applied as an
+// index map while loading (periodic wrap or zero-gradient clamp).  A tile
+// computes TF faces and the TF-1 cells between them; neighbouring tiles
+// overlap by one face.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "eno_device.hpp"
+
+namespace enomr {
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1 };
+enum { SYS_ADVECTION = 0, SYS_BURGERS = 1 };
+
+__device__ __forceinline__ long map_cell(long i, long n, int bc)
+{
+    if (bc == BC_PERIODIC) {
+        long k = i % n;
+        return k < 0 ? k + n : k;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ void flag_nonphysical(unsigned* status)
+{
+    atomicOr(status, 1u);
+}
+
+// Largest of non-negative doubles through their bit patterns (order preserving).
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v)
+{
+    atomicMax(reinterpret_cast<unsigned long long*>(addr),
+              static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill(double* p, long n, double v)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_set_int(int* p, int v)
+{
+    if (threadIdx.x == 0) *p = v;
+}
+
+// Scalar laws: alpha = max |f'(u)| over the line (|a| or max |u|).
+__global__ void k_alpha_scalar(const double* __restrict__ u, long n, int flux, double a,
+                               double* alpha, const int* active)
+{
+    if (active && *active == 0) return;
+    double m = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        m = fmax(m, flux == SYS_ADVECTION ? fabs(a) : fabs(u[i]));
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(alpha, m);
+}
+
+// Euler: alpha_x[y] = max_x(|u|+c), alpha_y[x] = max_y(|v|+c) (nv = 4);
+// nv = 3: alpha_x[0] = max(|u|+c).  Tile: 64 columns x (4*8) rows per block.
+template <int NV>
+__global__ __launch_bounds__(256) void k_alpha_euler(const double* __restrict__ U, long nx, long ny,
+                                                      double gamma, double* ax, double* ay,
+                                                      unsigned* status, const int* active)
+{
+    if (active && *active == 0) return;
+    __shared__ double col[4][64];
+    const long plane = nx * ny;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const long x = blockIdx.x * 64L + tx;
+    const long y0 = blockIdx.y * 32L;
+    const double gm1 = gamma - 1.0;
+    double cmax = 0.0;
+    for (int r = ty; r < 32; r += 4) {
+        const long y = y0 + r;
+        double sx = 0.0, sy = 0.0;
+        const bool ok = (x < nx) && (y < ny);
+        if (ok) {
+            const long g = y * nx + x;
+            const double rho = U[g], m = U[plane + g];
+            const double n = NV == 4 ? U[2 * plane + g] : 0.0;
+            const double E = U[(NV - 1) * plane + g];
+            const double ir = 1.0 / rho;
+            const double u = m * ir;
+            const double v = NV == 4 ? n * ir : 0.0;
+            const double ke = NV == 4 ? 0.5 * (m * u + n * v) : 0.5 * (m * u);
+            const double p = gm1 * (E - ke);
+            if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(m) || !isfinite(n))
+                flag_nonphysical(status);
+            const double c = sqrt((gamma * p) * ir);
+            sx = fabs(u) + c;
+            sy = fabs(v) + c;
+        }
+        const double rmax = wave_max(sx);
+        if (tx == 0 && y < ny) atomic_max_nonneg(&ax[y], rmax);
+        cmax = fmax(cmax, sy);
+    }
+    if (NV == 4) {
+        col[ty][tx] = cmax;
+        __syncthreads();
+        if (ty == 0 && x < nx) {
+            const double v = fmax(fmax(col[0][tx], col[1][tx]), fmax(col[2][tx], col[3][tx]));
+            atomic_max_nonneg(&ay[x], v);
+        }
+    }
+}
+
+// dt from the CFL rule (one block).  1D: dt = cfl / (ax[0] * ihx);
+// 2D: dt = cfl / (max(ax) * ihx + max(ay) * ihy).  With t_end > 0, the step
+// is cut to end at t_end and *active turns 0 once t has reached it.
+__global__ __launch_bounds__(256) void k_dt(const double* ax, long nax, const double* ay, long nay,
+                                            double cfl, double ihx, double ihy, double t_end,
+                                            double* dt, double* t, int* active, double* dt_log,
+                                            long step)
+{
+    __shared__ double red[2][4];
+    double sx = 0.0, sy = 0.0;
+    for (long i = threadIdx.x; i < nax; i += 256) sx = fmax(sx, ax[i]);
+    for (long i = threadIdx.x; i < nay; i += 256) sy = fmax(sy, ay[i]);
+    sx = wave_max(sx);
+    sy = wave_max(sy);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = sx;
+        red[1][threadIdx.x >> 6] = sy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sx = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+        sy = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+        double d = nay > 0 ? cfl / (sx * ihx + sy * ihy) : cfl / (sx * ihx);
+        if (t_end > 0.0) {
+            if (*active == 0 || *t >= t_end) {
+                *active = 0;
+                d = 0.0;
+            } else {
+                if (*t + d > t_end) d = t_end - *t;
+                *t = *t + d;
+            }
+        }
+        *dt = d;
+        if (dt_log) dt_log[step] = d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bare reconstruction at n faces (Sec. 3.2), window read from global memory.
+// ---------------------------------------------------------------------------
+
+template <int R, int S>
+__global__ __launch_bounds__(256) void k_recon_faces(const double* __restrict__ f, long n,
+                                                     double* __restrict__ fhat, uint8_t* idx)
+{
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    if (i >= n) return;
+    double w[2 * R - 1];
+    const long base = S > 0 ? i : i + 1;
+#pragma unroll
+    for (int k = 0; k < 2 * R - 1; ++k) w[k] = f[base + k];
+    int id;
+    fhat[i] = recon<R, S>(w, id);
+    if (idx) idx[i] = (uint8_t)id;
+}
+
+// ---------------------------------------------------------------------------
+// SSP-RK3 stage combination (Sec. 2.3, Eq. TVD3rdRK).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double rk_combine(int stage, double un, double us, double L, double dt)
+{
+    const double e = us + dt * L;
+    if (stage == 1) return e;
+    if (stage == 2) return 0.75 * un + 0.25 * e;
+    return (1.0 / 3.0) * un + (2.0 / 3.0) * e;
+}
+
+struct StageOut {
+    const double* Un;      // step-start state (RK mode)
+    const double* Lprev;   // operator part to add first (2D y-sweep), nullable
+    double* out;           // L (store mode) or the next stage state (RK mode)
+    const double* dt;      // device dt (RK mode)
+    int stage;             // 1..3; 0 = store L
+};
+
+// ---------------------------------------------------------------------------
+// Scalar conservation law on one line: LF split, f^+ and f^- reconstruction,
+// conservative difference, then store L or combine an RK stage.
+// ---------------------------------------------------------------------------
+
+template <int R, int TF>
+__global__ __launch_bounds__(TF) void k_scalar_sweep(const double* __restrict__ us, long n, double ih,
+                                                     int flux, double a, int split, int bc,
+                                                     const double* alpha, StageOut so, uint8_t* idx,
+                                                     const int* active)
+{
+    if (active && *active == 0) return;
+    constexpr int TC = TF - 1;
+    constexpr int NCL = TF + 2 * R - 1;
+    __shared__ double sp[NCL], sm[NCL], sf[TF];
+    const long c0 = blockIdx.x * (long)TC;
+    const double al = split ? *alpha : 0.0;
+    for (int e = threadIdx.x; e < NCL; e += TF) {
+        const double u = us[map_cell(c0 - R + e, n, bc)];
+        const double f = flux == SYS_ADVECTION ? a * u : 0.5 * u * u;
+        if (split) {
+            const double t = al * u;
+            sp[e] = 0.5 * (f + t);
+            sm[e] = 0.5 * (f - t);
+        } else {
+            sp[e] = f;
+            sm[e] = 0.0;
+        }
+    }
+    __syncthreads();
+    const int tf = threadIdx.x;
+    const long face = c0 + tf;
+    if (face <= n) {
+        const int jp = tf + R - 1;   // left cell of the face in LDS
+        double wp[2 * R - 1], wm[2 * R - 1];
+#pragma unroll
+        for (int k = 0; k < 2 * R - 1; ++k) {
+            wp[k] = sp[jp - (R - 1) + k];
+            wm[k] = sm[jp - (R - 2) + k];
+        }
+        int ip, im = 0;
+        const double hp = recon<R, +1>(wp, ip);
+        double hm = 0.0;
+        if (split) hm = recon<R, -1>(wm, im);
+        sf[tf] = hp + hm;
+        if (idx) {
+            idx[2 * face] = (uint8_t)ip;
+            idx[2 * face + 1] = (uint8_t)im;
+        }
+    }
+    __syncthreads();
+    const long cell = c0 + tf;
+    if (tf < TC && cell < n) {
+        double L = -((sf[tf + 1] - sf[tf]) * ih);
+        if (so.Lprev) L = so.Lprev[cell] + L;
+        if (so.stage == 0) so.out[cell] = L;
+        else so.out[cell] = rk_combine(so.stage, so.Un[cell], us[cell], L, *so.dt);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Euler: Roe-averaged eigenvectors at a face (Sec. 4 preamble) and the
+// characteristic sweep.
+// ---------------------------------------------------------------------------
+
+// Left/right eigenvectors of the face-normal flux Jacobian at the Roe state.
+// Fields (u-c, u, [shear,] u+c).  Rows of L and columns of R are kept as the
+// distinct entries of the closed forms.
+struct Eig {
+    double a0, a1, a3, a4;   // first two entries of the u-c and u+c rows of L
+    double C, D;             // last entries shared by those rows: -k v/2, k/2
+    double l20, ku, kv, k;   // the u row of L: (1 - k q^2/2, k u, k v, -k)
+    double u, v, c, H, uc, q2h;
+};
+
+template <int NV>
+__device__ __forceinline__ bool roe_eigen(double sL, double unL, double utL, double HL, double sR,
+                                          double unR, double utR, double HR, double gm1, Eig& e)
+{
+    const double id = 1.0 / (sL + sR);
+    const double u = (sL * unL + sR * unR) * id;
+    const double v = NV == 4 ? (sL * utL + sR * utR) * id : 0.0;
+    const double H = (sL * HL + sR * HR) * id;
+    const double q2 = NV == 4 ? u * u + v * v : u * u;
+    const double c2 = gm1 * (H - 0.5 * q2);
+    const double c = sqrt(c2);
+    const double k = gm1 / c2;
+    const double ic = 1.0 / c;
+    const double hq = 0.5 * k * q2;
+    const double ku = k * u;
+    const double uic = u * ic;
+    e.a0 = 0.5 * (hq + uic);
+    e.a1 = -0.5 * (ku + ic);
+    e.a3 = 0.5 * (hq - uic);
+    e.a4 = -0.5 * (ku - ic);
+    e.kv = k * v;
+    e.C = -0.5 * e.kv;
+    e.D = 0.5 * k;
+    e.l20 = 1.0 - hq;
+    e.ku = ku;
+    e.k = k;
+    e.u = u;
+    e.v = v;
+    e.c = c;
+    e.H = H;
+    e.uc = u * c;
+    e.q2h = 0.5 * q2;
+    return c2 > 0.0;
+}
+
+// w = L G for all fields; chains run over components 0..NV-1.  Structural
+// zeros of L are skipped and unit entries added (same value up to the sign
+// of a zero result).
+template <int NV>
+__device__ __forceinline__ void project(const Eig& e, const double (&G)[NV], double (&w)[NV])
+{
+    if constexpr (NV == 4) {
+        w[0] = fma(e.D, G[3], fma(e.C, G[2], fma(e.a1, G[1], e.a0 * G[0])));
+        w[1] = fma(-e.k, G[3], fma(e.kv, G[2], fma(e.ku, G[1], e.l20 * G[0])));
+        w[2] = (-e.v) * G[0] + G[2];
+        w[3] = fma(e.D, G[3], fma(e.C, G[2], fma(e.a4, G[1], e.a3 * G[0])));
+    } else {
+        w[0] = fma(e.D, G[2], fma(e.a1, G[1], e.a0 * G[0]));
+        w[1] = fma(-e.k, G[2], fma(e.ku, G[1], e.l20 * G[0]));
+        w[2] = fma(e.D, G[2], fma(e.a4, G[1], e.a3 * G[0]));
+    }
+}
+
+// Row k of L as a generic chain (slow path; k is uniform across the wave).
+template <int NV>
+__device__ __forceinline__ void l_row(const Eig& e, int k, double (&r)[NV])
+{
+    if constexpr (NV == 4) {
+        const bool f0 = k == 0, f1 = k == 1, f2 = k == 2;
+        r[0] = f0 ? e.a0 : (f1 ? e.l20 : (f2 ? -e.v : e.a3));
+        r[1] = f0 ? e.a1 : (f1 ? e.ku : (f2 ? 0.0 : e.a4));
+        r[2] = f0 ? e.C : (f1 ? e.kv : (f2 ? 1.0 : e.C));
+        r[3] = f0 ? e.D : (f1 ? -e.k : (f2 ? 0.0 : e.D));
+    } else {
+        const bool f0 = k == 0, f1 = k == 1;
+        r[0] = f0 ? e.a0 : (f1 ? e.l20 : e.a3);
+        r[1] = f0 ? e.a1 : (f1 ? e.ku : e.a4);
+        r[2] = f0 ? e.D : (f1 ? -e.k : e.D);
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ double row_chain(const double (&r)[NV], const double (&G)[NV])
+{
+    double acc = r[0] * G[0];
+#pragma unroll
+    for (int q = 1; q < NV; ++q) acc = fma(r[q], G[q], acc);
+    return acc;
+}
+
+// F-hat = R w-hat, chains over fields 0..NV-1.
+template <int NV>
+__device__ __forceinline__ void back_project(const Eig& e, const double (&w)[NV], double (&F)[NV])
+{
+    const double umc = e.u - e.c, upc = e.u + e.c;
+    const double hm = e.H - e.uc, hp = e.H + e.uc;
+    if constexpr (NV == 4) {
+        F[0] = (w[0] + w[1]) + w[3];
+        F[1] = fma(upc, w[3], fma(e.u, w[1], umc * w[0]));
+        F[2] = fma(e.v, w[3], fma(e.v, w[1], e.v * w[0]) + w[2]);
+        F[3] = fma(hp, w[3], fma(e.v, w[2], fma(e.q2h, w[1], hm * w[0])));
+    } else {
+        F[0] = (w[0] + w[1]) + w[2];
+        F[1] = fma(upc, w[2], fma(e.u, w[1], umc * w[0]));
+        F[2] = fma(hp, w[2], fma(e.q2h, w[1], hm * w[0]));
+    }
+}
+
+struct SweepIn {
+    const double* Us;      // state the operator is evaluated on
+    const double* alpha;   // per-line alpha (LF splitting)
+    unsigned* status;
+    uint8_t* idx;          // nullable: this direction's stencil log
+    const int* active;     // nullable
+    long nx, ny;
+    double ih, gamma;
+    int bc;
+};
+
+// Characteristic ENO-MR sweep.  DIR 0: lines are rows (x faces); DIR 1: lines
+// are columns (y faces), evaluated on the permuted state (rho, n, m, E) so the
+// same x-normal formulas apply.
+template <int NV, int R, int DIR, int TF, int TL>
+__global__ __launch_bounds__(TF* TL) void k_euler_sweep(SweepIn in, StageOut so)
+{
+    if (in.active && *in.active == 0) return;
+    constexpr int NT = TF * TL;
+    constexpr int TC = TF - 1;
+    constexpr int NCL = TF + 2 * R - 1;
+    constexpr int NCELL = NCL * TL;
+    constexpr int W = 2 * R - 1;
+    __shared__ double sGp[NV][NCELL];
+    __shared__ double sGm[NV][NCELL];
+    __shared__ double sSq[NCELL], sUn[NCELL], sH[NCELL];
+    __shared__ double sUt[NV == 4 ? NCELL : 1];
+    __shared__ double sF[NV][TF * TL];
+
+    const long nx = in.nx, ny = in.ny, plane = nx * ny;
+    const long nlines = DIR == 0 ? ny : nx;
+    const long n = DIR == 0 ? nx : ny;
+    const long line0 = (long)blockIdx.y * TL;
+    const long c0 = (long)blockIdx.x * TC;
+    const double gamma = in.gamma, gm1 = gamma - 1.0;
+    // normal-frame component q -> global variable
+    auto gvar = [](int q) { return (DIR == 1 && NV == 4) ? (q == 1 ? 2 : (q == 2 ? 1 : q)) : q; };
+    auto lpos = [](int line, int cell) { return DIR == 0 ? line * NCL + cell : cell * TL + line; };
+    auto gidx = [nx](long line, long cell) { return DIR == 0 ? line * nx + cell : cell * nx + line; };
+
+    // ---- stage the tile: primitives, LF split G = (F +- alpha U)/2, Roe inputs
+    for (int e = threadIdx.x; e < NCELL; e += NT) {
+        const int line = DIR == 0 ? e / NCL : e % TL;
+        const int cell = DIR == 0 ? e % NCL : e / TL;
+        const long gl = line0 + line;
+        if (gl >= nlines) continue;
+        const long g = gidx(gl, map_cell(c0 - R + cell, n, in.bc));
+        double Uc[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Uc[q] = in.Us[gvar(q) * plane + g];
+        const double rho = Uc[0], mn = Uc[1], E = Uc[NV - 1];
+        const double mt = NV == 4 ? Uc[2] : 0.0;
+        const double ir = 1.0 / rho;
+        const double un = mn * ir;
+        const double ut = NV == 4 ? mt * ir : 0.0;
+        const double ke = NV == 4 ? 0.5 * (mn * un + mt * ut) : 0.5 * (mn * un);
+        const double p = gm1 * (E - ke);
+        if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(mn)) flag_nonphysical(in.status);
+        double F[NV];
+        F[0] = mn;
+        F[1] = mn * un + p;
+        if constexpr (NV == 4) F[2] = mt * un;
+        F[NV - 1] = (E + p) * un;
+        const double al = in.alpha[gl];
+        const int lp = lpos(line, cell);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const double t = al * Uc[q];
+            sGp[q][lp] = 0.5 * (F[q] + t);
+            sGm[q][lp] = 0.5 * (F[q] - t);
+        }
+        sSq[lp] = sqrt(rho);
+        sUn[lp] = un;
+        if constexpr (NV == 4) sUt[lp] = ut;
+        sH[lp] = (E + p) * ir;
+    }
+    __syncthreads();
+
+    const int tf = DIR == 0 ? threadIdx.x % TF : threadIdx.x / TL;
+    const int tl = DIR == 0 ? threadIdx.x / TF : threadIdx.x % TL;
+    const long gl = line0 + tl;
+    const long face = c0 + tf;
+    const bool live = gl < nlines && face <= n;
+
+    if (live) {
+        const int jp = tf + R - 1;   // left cell of the face in the tile
+        const int pl = lpos(tl, jp), pr = lpos(tl, jp + 1);
+        Eig e;
+        const bool ok = roe_eigen<NV>(sSq[pl], sUn[pl], NV == 4 ? sUt[pl] : 0.0, sH[pl], sSq[pr], sUn[pr],
+                                      NV == 4 ? sUt[pr] : 0.0, sH[pr], gm1, e);
+        if (!ok) flag_nonphysical(in.status);
+
+        // ---- smooth path: stream the window once, accumulating for every
+        // field and sign the full-stencil indicator and flux and keeping the
+        // five central values for IS0.
+        constexpr int P0 = cand_pool(R, 0);
+        double isp[NV], flp[NV], ism[NV], flm[NV];
+        double cp[5][NV], cm[5][NV];   // centre +-2: + frame cells j-2..j+2, - frame j-1..j+3
+#pragma unroll
+        for (int o = -R + 1; o <= R; ++o) {
+            const int lp = lpos(tl, jp + o);
+            if (o <= R - 1) {
+                double G[NV], w[NV];
+#pragma unroll
+                for (int q = 0; q < NV; ++q) G[q] = sGp[q][lp];
+                project<NV>(e, G, w);
+                const int ci = o + (R - 1);
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    if (o == -R + 1) {
+                        isp[q] = c_b[P0][ci] * w[q];
+                        flp[q] = c_a[P0][ci] * w[q];
+                    } else {
+                        isp[q] = fma(c_b[P0][ci], w[q], isp[q]);
+                        flp[q] = fma(c_a[P0][ci], w[q], flp[q]);
+                    }
+                    if (o >= -2 && o <= 2) cp[o + 2][q] = w[q];
+                }
+            }
+            if (o >= -R + 2) {
+                double G[NV], w[NV];
+#pragma unroll
+                for (int q = 0; q < NV; ++q) G[q] = sGm[q][lp];
+                project<NV>(e, G, w);
+                const int ci = R - o;
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    if (o == -R + 2) {
+                        ism[q] = c_b[P0][ci] * w[q];
+                        flm[q] = c_a[P0][ci] * w[q];
+                    } else {
+                        ism[q] = fma(c_b[P0][ci], w[q], ism[q]);
+                        flm[q] = fma(c_a[P0][ci], w[q], flm[q]);
+                    }
+                    if (o >= -1 && o <= 3) cm[o + 1][q] = w[q];
+                }
+            }
+        }
+
+        double hp[NV], hm[NV];
+        unsigned fail = 0;
+        uint64_t idxw = 0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            // + frame: centre cp[2]; left neighbours cp[1], cp[0]; right cp[3], cp[4]
+            {
+                const double f0 = cp[2][q], fm1 = cp[1][q], fm2 = cp[0][q], fp1 = cp[3][q], fp2 = cp[4][q];
+                const double is0 = fmin(fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2)),
+                                        fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2)));
+                hp[q] = flp[q];
+                if (!(fabs(isp[q]) < is0)) fail |= 1u << (2 * q);
+            }
+            // - frame: centre cell j+1 = cm[2]; its upwind side is j+2, j+3
+            {
+                const double f0 = cm[2][q], fm1 = cm[3][q], fm2 = cm[4][q], fp1 = cm[1][q], fp2 = cm[0][q];
+                const double is0 = fmin(fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2)),
+                                        fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2)));
+                hm[q] = flm[q];
+                if (!(fabs(ism[q]) < is0)) fail |= 1u << (2 * q + 1);
+            }
+        }
+
+        // ---- remaining candidates for the (field, sign) pairs that failed
+        if (fail) {
+#pragma unroll 1
+            for (int kk = 0; kk < 2 * NV; ++kk) {
+                if (!((fail >> kk) & 1u)) continue;
+                const int q = kk >> 1;
+                double r[NV];
+                l_row<NV>(e, q, r);
+                double w[W];
+                int id;
+                double res;
+                if ((kk & 1) == 0) {
+#pragma unroll
+                    for (int i = 0; i < W; ++i) {
+                        const int lp = lpos(tl, jp - (R - 1) + i);
+                        double G[NV];
+#pragma unroll
+                        for (int c = 0; c < NV; ++c) G[c] = sGp[c][lp];
+                        w[i] = row_chain<NV>(r, G);
+                    }
+                    res = select_from<R, +1, 1>(w, baseline_is<R, +1>(w), id);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < W; ++i) {
+                        const int lp = lpos(tl, jp - (R - 2) + i);
+                        double G[NV];
+#pragma unroll
+                        for (int c = 0; c < NV; ++c) G[c] = sGm[c][lp];
+                        w[i] = row_chain<NV>(r, G);
+                    }
+                    res = select_from<R, -1, 1>(w, baseline_is<R, -1>(w), id);
+                }
+#pragma unroll
+                for (int t = 0; t < NV; ++t) {
+                    if (t == q) {
+                        if ((kk & 1) == 0) hp[t] = res;
+                        else hm[t] = res;
+                    }
+                }
+                idxw |= (uint64_t)(uint8_t)id << (8 * kk);
+            }
+        }
+
+        double wh[NV], Fh[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) wh[q] = hp[q] + hm[q];
+        back_project<NV>(e, wh, Fh);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sF[q][tl * TF + tf] = Fh[q];
+
+        if (in.idx) {
+            uint8_t* dst = DIR == 0 ? in.idx + ((gl * (n + 1) + face) * NV) * 2
+                                    : in.idx + ((face * nx + gl) * NV) * 2;
+#pragma unroll
+            for (int b = 0; b < 2 * NV; ++b) dst[b] = (uint8_t)(idxw >> (8 * b));
+        }
+    }
+    __syncthreads();
+
+    // ---- conservative difference and output
+    const long cell = c0 + tf;
+    if (gl < nlines && tf < TC && cell < n) {
+        const long g = gidx(gl, cell);
+        const double dt = so.stage ? *so.dt : 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const int v = gvar(q);
+            double L = -((sF[q][tl * TF + tf + 1] - sF[q][tl * TF + tf]) * in.ih);
+            if (so.Lprev) L = so.Lprev[v * plane + g] + L;
+            if (so.stage == 0) so.out[v * plane + g] = L;
+            else so.out[v * plane + g] = rk_combine(so.stage, so.Un[v * plane + g], in.Us[v * plane + g], L, dt);
+        }
+    }
+}
+
+}  // namespace enomr

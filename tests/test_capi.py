@@ -1,0 +1,71 @@
+"""The C-ABI library loads, exports what include/enomr.h declares, and its
+host-side coefficient tables equal the paper's and the oracle's.  No GPU."""
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import paper_2311_15504_amd as enomr
+from oracle import coeffs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _declared_symbols():
+    with open(os.path.join(ROOT, "include", "enomr.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(enomr_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = enomr.lib()
+    names = _declared_symbols()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_library_coefficients_equal_oracle_doubles_bitwise():
+    # The library derives a_l from Lagrange derivatives of the primitive and
+    # b_l from binomials; the oracle solves the moment system exactly.  Both
+    # round to the nearest double, so the tables must agree bit for bit.
+    for order in coeffs.ORDERS:
+        mn, a, b = enomr.coefficients(order)
+        rows = coeffs.double_table(order)
+        assert mn.shape[0] == len(rows)
+        for c, (m, n, al, bl) in enumerate(rows):
+            assert tuple(mn[c]) == (m, n)
+            assert np.array_equal(a[c, :m + n + 1], np.array(al))
+            assert np.array_equal(b[c, :m + n + 1], np.array(bl))
+            assert np.all(a[c, m + n + 1:] == 0)
+
+
+def test_library_coefficients_equal_printed_tables():
+    mn, a, _ = enomr.coefficients(17)
+    pos = {tuple(x): i for i, x in enumerate(mn)}
+    with open(os.path.join(GOLDEN, "a_coefficients.txt")) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            m, n, l, num, den, _ = line.split()
+            m, n, l = int(m), int(n), int(l)
+            assert a[pos[(m, n)], l + m] == float(Fraction(int(num), int(den)))
+
+
+def test_bad_arguments_are_rejected_without_a_gpu():
+    with pytest.raises(enomr.EnomrError) as e:
+        enomr.coefficients(8)
+    assert e.value.status == 2
+    prob = enomr.Problem.euler2d(64, 64, 0.1, 0.1, 19)
+    with pytest.raises(enomr.EnomrError) as e:
+        enomr.workspace_size(prob)
+    assert e.value.status == 2
+    prob = enomr.Problem.euler2d(10, 64, 0.1, 0.1, 17)     # nx < 2r+1
+    with pytest.raises(enomr.EnomrError) as e:
+        enomr.workspace_size(prob)
+    assert e.value.status == 1
+    prob = enomr.Problem.euler2d(2048, 2048, 1 / 1024, 1 / 1024, 17)
+    assert enomr.workspace_size(prob) >= 3 * 4 * 2048 * 2048 * 8

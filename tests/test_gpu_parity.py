@@ -1,0 +1,272 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: stencil indices identical; the operator L(U) within 1e-12 relative per
+variable per stage; states after full runs within 1e-10 (max norm, relative
+to max(1, |U|)).  The kernels evaluate every formula in the oracle's order, so
+most comparisons are in fact bitwise; the tests report that too.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+STAGE_TOL = 1e-12
+FINAL_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_15504_amd as enomr
+    c = enomr.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _assert_stage_close(got, ref, what):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    for v in range(ref.shape[0]):
+        scale = np.abs(ref[v]).max()
+        err = np.abs(got[v] - ref[v]).max()
+        assert err <= STAGE_TOL * scale + 1e-300, (what, v, err, scale)
+
+
+# ---------------------------------------------------------------------------
+# Bare reconstruction (Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order", [5, 7, 9, 11, 13, 15, 17])
+@pytest.mark.parametrize("sign", [1, -1])
+def test_recon_faces_bitwise(ctx, order, sign):
+    rng = np.random.default_rng(order * 10 + (sign > 0))
+    n = 3000                                            # several blocks and a ragged tail
+    r = (order + 1) // 2
+    x = np.arange(n + 2 * r - 1) / 500.0
+    f = workloads.smooth_sines(order, x, 1.0)
+    f[700:] += 1.5                                      # a jump
+    f[1500:1600] = rng.standard_normal(100)             # rough patch: every candidate exercised
+    f[2000:2100] = 0.25                                 # constant patch: IS0 = 0 -> minmod
+    ref, ridx = oracle.recon_faces(order, sign, f)
+    got, gidx = ctx.recon_faces(order, sign, _dev(f))
+    got, gidx = _host(got), _host(gidx)
+    assert np.array_equal(gidx, ridx)
+    assert np.array_equal(got, ref)
+    assert len(set(ridx.tolist())) > 3                  # not only the full stencil
+
+
+def test_recon_faces_empty_and_tiny(ctx):
+    import torch
+    got, idx = ctx.recon_faces(9, 1, _dev(np.zeros(9 - 1 + 0)))
+    assert got.numel() == 0
+    f = np.linspace(0, 1, 17 + 1)
+    ref, ridx = oracle.recon_faces(17, 1, f)
+    got, gidx = ctx.recon_faces(17, 1, _dev(f))
+    assert np.array_equal(_host(got), ref) and np.array_equal(_host(gidx), ridx)
+
+
+# ---------------------------------------------------------------------------
+# Scalar laws
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order", [5, 9, 13, 17])
+def test_advection_operator_bitwise(ctx, order):
+    import paper_2311_15504_amd as enomr
+    _, h, u = workloads.advection_sines_step(order, 200)
+    ref, ridx, _ = oracle.scalar_rhs(order, u, h, with_idx=True)
+    prob = enomr.Problem.scalar(enomr.ADVECTION, 200, h, order)
+    got, gidx = ctx.rhs(prob, _dev(u[None]), with_idx=True)
+    assert np.array_equal(_host(gidx).reshape(-1, 2), ridx)
+    assert np.array_equal(_host(got)[0], ref)
+
+
+@pytest.mark.parametrize("order", [5, 17])
+def test_burgers_operator_bitwise(ctx, order):
+    import paper_2311_15504_amd as enomr
+    _, h, u = workloads.burgers_sin3(1.0, 256)
+    ref, ridx, _ = oracle.scalar_rhs(order, u, h, flux=oracle.BURGERS, split=oracle.SPLIT_NONE, with_idx=True)
+    prob = enomr.Problem.scalar(enomr.BURGERS, 256, h, order, split=enomr.SPLIT_NONE)
+    got, gidx = ctx.rhs(prob, _dev(u[None]), with_idx=True)
+    assert np.array_equal(_host(gidx).reshape(-1, 2), ridx)
+    assert np.array_equal(_host(got)[0], ref)
+
+
+def test_advection_full_run_matches_oracle(ctx):
+    # 1D linear advection, N = 200, 5th order, SSP-RK3 at CFL 0.5 to t = 2.
+    import paper_2311_15504_amd as enomr
+    _, h, u0 = workloads.advection_sines_step(0, 200)
+    ref = oracle.scalar_ssprk3_run(5, u0, h, 0.5 * h, nsteps=400)
+    prob = enomr.Problem.scalar(enomr.ADVECTION, 200, h, 5)
+    U = _dev(u0[None])
+    ctx.advance(prob, U, 0.5, 400)
+    ctx.check()
+    got = _host(U)[0]
+    assert np.abs(got - ref).max() <= FINAL_TOL * max(1.0, np.abs(ref).max())
+    assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------------------
+# Euler 1D
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order", [5, 7, 9, 11, 13, 15, 17])
+def test_euler1d_operator(ctx, order):
+    import paper_2311_15504_amd as enomr
+    _, h, U = workloads.euler1d_riemann_perturbed(order, 1000)
+    ref, ridx, _ = oracle.euler1d_rhs(order, U, h, with_idx=True)
+    prob = enomr.Problem.euler1d(1000, h, order)
+    got, gidx = ctx.rhs(prob, _dev(U), with_idx=True)
+    ctx.check()
+    assert np.array_equal(_host(gidx).reshape(-1, 3, 2), ridx)
+    _assert_stage_close(_host(got), ref, "euler1d")
+    assert np.array_equal(_host(got), ref)
+
+
+def test_euler1d_periodic_and_lax(ctx):
+    import paper_2311_15504_amd as enomr
+    _, h, U = workloads.euler1d_smooth_periodic(3, 300)
+    ref = oracle.euler1d_rhs(9, U, h, bc=oracle.PERIODIC)
+    got = ctx.rhs(enomr.Problem.euler1d(300, h, 9, bc=enomr.PERIODIC), _dev(U))
+    assert np.array_equal(_host(got), ref)
+    _, h, U = workloads.euler1d_lax(200)
+    ref = oracle.euler1d_rhs(17, U, h)
+    got = ctx.rhs(enomr.Problem.euler1d(200, h, 17), _dev(U))
+    assert np.array_equal(_host(got), ref)
+
+
+def test_euler1d_run_matches_oracle(ctx):
+    # The 1D Euler workload (seeded Riemann step with a density wave), 9th
+    # order, CFL 0.5, at reduced length and step count for the oracle.
+    import paper_2311_15504_amd as enomr
+    _, h, U0 = workloads.euler1d_riemann_perturbed(0, 512)
+    ref, dts = oracle.euler1d_run(9, U0, h, 60, cfl=0.5)
+    prob = enomr.Problem.euler1d(512, h, 9)
+    U = _dev(U0)
+    import torch
+    dt_log = torch.zeros(60, dtype=torch.float64, device="cuda")
+    ctx.advance(prob, U, 0.5, 60, dt_log=dt_log)
+    ctx.check()
+    assert np.array_equal(_host(dt_log), np.array(dts))
+    got = _host(U)
+    assert np.abs(got - ref).max() <= FINAL_TOL * max(1.0, np.abs(ref).max())
+
+
+# ---------------------------------------------------------------------------
+# Euler 2D
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order", [5, 9, 13, 17])
+def test_euler2d_operator(ctx, order):
+    import paper_2311_15504_amd as enomr
+    nx, ny = 150, 70                                   # ragged against both tile shapes
+    (x, y, hx, hy), U = workloads.euler2d_quadrants_vortices(order, nx, ny)
+    ref, ix, iy, _, _ = oracle.euler2d_rhs(order, U, hx, hy, with_idx=True)
+    prob = enomr.Problem.euler2d(nx, ny, hx, hy, order)
+    got, gidx = ctx.rhs(prob, _dev(U), with_idx=True)
+    ctx.check()
+    gidx = _host(gidx)
+    nxf = ny * (nx + 1) * 8
+    assert np.array_equal(gidx[:nxf].reshape(ny, nx + 1, 4, 2), ix)
+    assert np.array_equal(gidx[nxf:].reshape(ny + 1, nx, 4, 2), iy)
+    _assert_stage_close(_host(got), ref, "euler2d")
+    assert np.array_equal(_host(got), ref)
+
+
+def test_euler2d_riemann_configurations(ctx):
+    import paper_2311_15504_amd as enomr
+    for cfg in (1, 2):
+        (x, y, hx, hy), U = workloads.euler2d_riemann(cfg, 96, 80)
+        for bcx, bcy in ((enomr.OUTFLOW, enomr.OUTFLOW), (enomr.PERIODIC, enomr.PERIODIC)):
+            ref = oracle.euler2d_rhs(13, U, hx, hy, bcx=bcx, bcy=bcy)
+            got = ctx.rhs(enomr.Problem.euler2d(96, 80, hx, hy, 13, bcx, bcy), _dev(U))
+            assert np.array_equal(_host(got), ref)
+
+
+def test_euler2d_run_matches_oracle(ctx):
+    import paper_2311_15504_amd as enomr
+    nx = ny = 64
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(0, nx, ny)
+    ref, dts = oracle.euler2d_run(17, U0, hx, hy, 8, cfl=0.5)
+    prob = enomr.Problem.euler2d(nx, ny, hx, hy, 17)
+    U = _dev(U0)
+    ctx.advance(prob, U, 0.5, 8)
+    ctx.check()
+    got = _host(U)
+    assert np.abs(got - ref).max() <= FINAL_TOL * max(1.0, np.abs(ref).max())
+
+
+def test_euler2d_full_size_sampled(ctx):
+    # The 2048^2, 17th-order workload as the benchmark runs it: the operator
+    # at sampled cells against the oracle's one-cell evaluation, on the
+    # initial state and after two GPU steps.
+    import paper_2311_15504_amd as enomr
+    import torch
+    n = 2048
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(0, n, n)
+    prob = enomr.Problem.euler2d(n, n, hx, hy, 17)
+    U = _dev(U0)
+    rng = np.random.default_rng(5)
+    cells = np.stack([rng.integers(0, n, 24), rng.integers(0, n, 24)], axis=1)
+    cells = np.concatenate([cells, [[0, 0], [n - 1, n - 1], [0, n - 1], [n - 1, 0]]])
+    for step in range(2):
+        got = _host(ctx.rhs(prob, U))
+        Uh = _host(U)
+        ref = oracle.euler2d_rhs_cells(17, Uh, hx, hy, cells)
+        for k, (cx, cy) in enumerate(cells):
+            g = got[:, cy, cx]
+            scale = np.abs(ref[k]).max() + 1e-300
+            assert np.abs(g - ref[k]).max() <= STAGE_TOL * max(scale, 1.0), (step, cx, cy, g, ref[k])
+        ctx.advance(prob, U, 0.5, 1)
+    ctx.check()
+
+
+# ---------------------------------------------------------------------------
+# dt, status, determinism
+# ---------------------------------------------------------------------------
+
+def test_dt_matches_oracle(ctx):
+    import paper_2311_15504_amd as enomr
+    (x, y, hx, hy), U = workloads.euler2d_quadrants_vortices(2, 100, 90)
+    d = ctx.dt(enomr.Problem.euler2d(100, 90, hx, hy, 9), _dev(U), 0.5)
+    assert _host(d)[0] == oracle.dt_2d(U, hx, hy, 0.5)
+    _, h, U1 = workloads.euler1d_riemann_perturbed(4, 300)
+    d = ctx.dt(enomr.Problem.euler1d(300, h, 9), _dev(U1), 0.5)
+    assert _host(d)[0] == oracle.dt_1d(U1, h, 0.5)
+
+
+def test_nonphysical_state_is_reported(ctx):
+    import paper_2311_15504_amd as enomr
+    _, h, U = workloads.euler1d_riemann_perturbed(1, 200)
+    U = U.copy()
+    U[0, 77] = -0.1                                     # negative density
+    with pytest.raises(enomr.EnomrError) as e:
+        ctx.rhs(enomr.Problem.euler1d(200, h, 9), _dev(U))
+        ctx.check()
+    assert e.value.status == 5
+    ctx.check()                                         # cleared
+
+
+def test_runs_are_deterministic(ctx):
+    import paper_2311_15504_amd as enomr
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(9, 256, 256)
+    prob = enomr.Problem.euler2d(256, 256, hx, hy, 13)
+    A = _dev(U0)
+    B = _dev(U0)
+    ctx.advance(prob, A, 0.5, 3)
+    ctx.advance(prob, B, 0.5, 3)
+    ctx.check()
+    assert np.array_equal(_host(A), _host(B))
