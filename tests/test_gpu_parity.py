@@ -70,9 +70,12 @@ def test_recon_faces_bitwise(ctx, order, sign):
 
 
 def test_recon_faces_empty_and_tiny(ctx):
-    import torch
-    got, idx = ctx.recon_faces(9, 1, _dev(np.zeros(9 - 1 + 0)))
+    import paper_2311_15504_amd as enomr
+    got, idx = ctx.recon_faces(9, 1, _dev(np.zeros(9)))       # 2r-1 values: zero faces
     assert got.numel() == 0
+    with pytest.raises(enomr.EnomrError) as e:                 # too short for one window
+        ctx.recon_faces(9, 1, _dev(np.zeros(8)))
+    assert e.value.status == 1
     f = np.linspace(0, 1, 17 + 1)
     ref, ridx = oracle.recon_faces(17, 1, f)
     got, gidx = ctx.recon_faces(17, 1, _dev(f))
