@@ -1,0 +1,214 @@
+"""Throughput of the ENO-MR hot path on one MI355X.
+
+A step is one SSP-RK3 step (three stages) of the 2D Euler equations on the
+2048 x 2048 grid with 17th-order characteristic ENO-MR (x periodic, y
+outflow, CFL 0.5): per-line alphas, dt, LF splitting, Roe projection, stencil
+selection, back-projection, conservative difference and the stage
+combination, all in the library's kernels.  The state starts resident in HBM.
+
+Prints one JSON line: cell-updates per second per RK stage (cells x stages /
+wall time), the roofline of the dominant kernel (FP64 vector ALU), and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ENO-MR cell-updates/s per RK stage (FP64), % of roofline; adjoint/fwd ratio"
+PEAK_FP64_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz
+
+
+def algorithmic_flops_per_face(order, nv=4):
+    """FP64 flops (FMA = 2) of one face on the smooth path, as the method needs them.
+
+    Roe average and eigenvectors (41); projection of both split fluxes over the
+    two (2r-1)-cell windows (23 per cell and sign: three 4-term rows and the
+    2-term shear row); full-stencil IS and flux chains for every field and sign
+    (2 x (4r-3)); the baseline indicators IS0 and the comparison (12 per field
+    and sign); back-projection (28).
+    """
+    assert nv == 4
+    r = (order + 1) // 2
+    return 41 + 46 * (2 * r - 1) + 16 * (4 * r - 3) + 96 + 28
+
+
+def extra_flops_table(order):
+    """Extra flops of a (field, sign) reconstruction that chose candidate C.
+
+    Candidates 1..C are tested (IS chain plus compare: 2 (m+n+1)) and the chosen
+    one's flux is evaluated (2 (m+n+1) - 1); minmod fallbacks test every
+    candidate with m, n >= 1 and add 6 flops.
+    """
+    import paper_2311_15504_amd as enomr
+    mn, _, _ = enomr.coefficients(order)
+    nc = mn.shape[0]
+    last_full = nc - 4                      # candidates with m, n >= 1 are 0..nc-4
+    tab = np.zeros(256)
+    for C in range(1, nc):
+        tested = range(1, min(C, last_full) + 1)
+        e = sum(2 * (mn[c, 0] + mn[c, 1] + 1) for c in tested)
+        if C <= last_full:
+            e += 2 * (mn[C, 0] + mn[C, 1] + 1) - 1
+        else:
+            e += 6
+        tab[C] = e
+    return tab
+
+
+def cell_flops(stage_out):
+    """Per-cell flops of a sweep: staging (36) plus the output (x: 8; y with RK: 32)."""
+    return 36 + stage_out
+
+
+def run(args):
+    import torch
+
+    import paper_2311_15504_amd as enomr
+    import workloads
+
+    n = args.n
+    order = args.order
+    cfl = 0.5
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(args.seed, n, n)
+    prob = enomr.Problem.euler2d(n, n, hx, hy, order, enomr.PERIODIC, enomr.OUTFLOW)
+    ctx = enomr.Context(0)
+    U0d = torch.from_numpy(U0).cuda()
+    U = U0d.clone()
+    ctx.workspace(prob)
+
+    # warm-up
+    ctx.advance(prob, U, cfl, args.warmup)
+    ctx.check()
+    torch.cuda.synchronize()
+
+    # timed region: K steps, per-kernel HIP events inside the library
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ctx.profile_start()
+    t0.record(stream)
+    ctx.advance(prob, U, cfl, args.steps)
+    t1.record(stream)
+    prof = ctx.profile_stop()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ctx.check()
+    ms = t0.elapsed_time(t1)
+    cells = n * n
+    value = cells * 3 * args.steps / (ms * 1e-3)
+
+    # algorithmic work of the same K steps: replay them (bitwise identical)
+    # with stencil logs and count what each face needed.
+    U.copy_(U0d)
+    ctx.advance(prob, U, cfl, args.warmup)
+    ib = prob.idx_bytes()
+    log = torch.empty(3 * ib, dtype=torch.uint8, device="cuda")
+    nxf = n * (n + 1) * 8
+    hist_x = torch.zeros(256, dtype=torch.float64, device="cuda")
+    hist_y = torch.zeros(256, dtype=torch.float64, device="cuda")
+    for _ in range(args.steps):
+        dt = ctx.dt(prob, U, cfl)
+        ctx.ssprk3_step(prob, U, dt, log)
+        for s in range(3):
+            seg = log[s * ib:(s + 1) * ib]
+            # x faces: [ny][nx+1][4][2]; face nx repeats face 0 (periodic x)
+            xs = seg[:nxf].view(n, n + 1, 8)[:, :n, :].reshape(-1)
+            ys = seg[nxf:]
+            hist_x += torch.bincount(xs.long(), minlength=256).double()
+            hist_y += torch.bincount(ys.long(), minlength=256).double()
+    ctx.check()
+    extra = torch.from_numpy(extra_flops_table(order)).cuda()
+    launches = 3 * args.steps
+    face_fl = algorithmic_flops_per_face(order)
+    fl_x = (n * n * face_fl + n * n * cell_flops(8)) * launches + float((hist_x * extra).sum())
+    fl_y = ((n + 1) * n * face_fl + n * n * cell_flops(32)) * launches + float((hist_y * extra).sum())
+    ms_x, nl_x = prof["sweep_x"]
+    ms_y, nl_y = prof["sweep_y"]
+    # dominant kernel: the sweep with the larger total time
+    if ms_y >= ms_x:
+        dom, fl, kms, nl = "k_euler_sweep (y faces)", fl_y, ms_y, nl_y
+    else:
+        dom, fl, kms, nl = "k_euler_sweep (x faces)", fl_x, ms_x, nl_x
+    per_launch = fl / launches
+    avg_ms = kms / nl
+    achieved = per_launch / (avg_ms * 1e-3) / 1e12
+    smooth_frac_x = float(hist_x[0] / hist_x.sum())
+    smooth_frac_y = float(hist_y[0] / hist_y.sum())
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D Euler %dx%d, ENO-MR order %d, characteristic LF, SSP-RK3 CFL 0.5, "
+                               "x periodic / y outflow, seeded quadrants + 8 isentropic vortices" % (n, n, order),
+                   "nx": n, "ny": n, "order": order, "cfl": cfl, "seed": args.seed},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
+                     "algorithmic_flop_per_launch": per_launch, "avg_launch_ms": avg_ms},
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "full_stencil_fraction": {"x": smooth_frac_x, "y": smooth_frac_y},
+        "wall_s": wall,
+    }
+    ctx.close()
+    return out
+
+
+def cpu_baseline(args):
+    """The oracle (single thread) on a 512 x 512 window of the same initial state, one step."""
+    import oracle
+    import workloads
+
+    n = args.n
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(args.seed, n, n)
+    m = min(512, n)
+    a = (n - m) // 2
+    sub = np.ascontiguousarray(U0[:, a:a + m, a:a + m])
+    oracle.lib()
+    t = time.perf_counter()
+    oracle.euler2d_run(args.order, sub, hx, hy, 1, cfl=0.5, bcx=oracle.OUTFLOW, bcy=oracle.OUTFLOW)
+    dt = time.perf_counter() - t
+    return {"value": m * m * 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "one SSP-RK3 step of the central %dx%d window of the same initial state "
+                      "(order %d, outflow on both axes), single thread, %.1f s" % (m, m, args.order, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--order", type=int, default=17)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    out = run(args)
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -154,6 +154,17 @@ enomr_status enomr_advance(enomr_ctx *ctx, const enomr_problem *prob, double *U,
    (ENOMR_OK or ENOMR_ENONPHYS). */
 enomr_status enomr_check(enomr_ctx *ctx);
 
+/*
+ * Kernel timing.  Between enomr_profile_start() and enomr_profile_stop() every
+ * launch the context makes is bracketed by HIP events on its stream.  stop()
+ * waits for the stream and writes, per kernel class, the summed device time in
+ * milliseconds (ms[3]) and the number of launches (launches[3]); classes:
+ * 0 = x (or 1D) sweep kernels, 1 = y sweep kernels, 2 = alpha / dt / fills.
+ * Either pointer may be NULL.
+ */
+enomr_status enomr_profile_start(enomr_ctx *ctx);
+enomr_status enomr_profile_stop(enomr_ctx *ctx, double *ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

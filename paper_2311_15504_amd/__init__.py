@@ -93,6 +93,8 @@ def lib():
             "enomr_ssprk3_step": ([_vp, P, _vp, _vp, _vp, _vp], st),
             "enomr_advance": ([_vp, P, _vp, ctypes.c_double, ctypes.c_int64, ctypes.c_double, _vp, _vp], st),
             "enomr_check": ([_vp], st),
+            "enomr_profile_start": ([_vp], st),
+            "enomr_profile_stop": ([_vp, _vp, _vp], st),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -215,3 +217,14 @@ class Context:
     def check(self):
         self._sync_stream()
         _call("enomr_check", self.handle)
+
+    def profile_start(self):
+        _call("enomr_profile_start", self.handle)
+
+    def profile_stop(self):
+        """{class: (milliseconds, launches)} for 'sweep_x', 'sweep_y', 'aux'."""
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 3)()
+        self._sync_stream()
+        _call("enomr_profile_stop", self.handle, ctypes.cast(ms, _vp), ctypes.cast(n, _vp))
+        return {k: (ms[i], n[i]) for i, k in enumerate(("sweep_x", "sweep_y", "aux"))}

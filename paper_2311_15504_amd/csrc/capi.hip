@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/enomr.h"
 #include "kernels.hpp"
@@ -12,14 +14,23 @@
 namespace enomr {
 __constant__ double c_a[kPool][kMaxW];
 __constant__ double c_b[kPool][kMaxW];
+__constant__ double c_wa[2][kPool][kMaxW];
+__constant__ double c_wb[2][kPool][kMaxW];
+__constant__ int c_candpool[10][kPool];
 }  // namespace enomr
 
 using namespace enomr;
+
+enum { PROF_SWEEP_X = 0, PROF_SWEEP_Y = 1, PROF_AUX = 2, PROF_CLASSES = 3 };
 
 struct enomr_ctx {
     int device;
     hipStream_t stream;
     unsigned* status;   // device word, latched non-physical flag
+    // kernel timing (enomr_profile_start/stop): HIP event pairs per class
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[PROF_CLASSES];
+    size_t used[PROF_CLASSES] = {0, 0, 0};
 };
 
 namespace {
@@ -100,6 +111,29 @@ T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws)
 
 unsigned blocks_for(long n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// Bracket a launch with HIP events of class `cls` when profiling is on.
+template <typename F>
+void timed(enomr_ctx* ctx, int cls, F&& launch)
+{
+    if (!ctx->prof) {
+        launch();
+        return;
+    }
+    auto& v = ctx->ev[cls];
+    if (ctx->used[cls] == v.size()) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            launch();
+            return;
+        }
+        v.emplace_back(a, b);
+    }
+    auto& pr = v[ctx->used[cls]++];
+    (void)hipEventRecord(pr.first, ctx->stream);
+    launch();
+    (void)hipEventRecord(pr.second, ctx->stream);
+}
+
 #define DISPATCH_R(order, ...)                      \
     switch (((order) + 1) / 2) {                    \
     case 3: { constexpr int R = 3; __VA_ARGS__; } break;  \
@@ -125,21 +159,23 @@ enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* 
     double* ax = at<double>(ws, w.ax);
     double* ay = at<double>(ws, w.ay);
     const long nax = p.ny, nay = p.ndim == 2 ? p.nx : 1;
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(nax, 256)), dim3(256), 0, ctx->stream, ax, nax, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(nay, 256)), dim3(256), 0, ctx->stream, ay, nay, 0.0);
-    if (p.system == ENOMR_EULER) {
-        dim3 grid(blocks_for(p.nx, 64), blocks_for(p.ny, 32));
-        if (p.ndim == 2)
-            hipLaunchKernelGGL(k_alpha_euler<4>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
-                               p.gamma, ax, ay, ctx->status, active);
-        else
-            hipLaunchKernelGGL(k_alpha_euler<3>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
-                               p.gamma, ax, ay, ctx->status, active);
-    } else {
-        const unsigned nb = blocks_for(p.nx, 256) < 64 ? blocks_for(p.nx, 256) : 64;
-        hipLaunchKernelGGL(k_alpha_scalar, dim3(nb), dim3(256), 0, ctx->stream, Us, (long)p.nx,
-                           p.system == ENOMR_ADVECTION ? SYS_ADVECTION : SYS_BURGERS, p.adv_speed, ax, active);
-    }
+    timed(ctx, PROF_AUX, [&] {
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(nax, 256)), dim3(256), 0, ctx->stream, ax, nax, 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(nay, 256)), dim3(256), 0, ctx->stream, ay, nay, 0.0);
+        if (p.system == ENOMR_EULER) {
+            dim3 grid(blocks_for(p.nx, 64), blocks_for(p.ny, 32));
+            if (p.ndim == 2)
+                hipLaunchKernelGGL(k_alpha_euler<4>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
+                                   p.gamma, ax, ay, ctx->status, active);
+            else
+                hipLaunchKernelGGL(k_alpha_euler<3>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
+                                   p.gamma, ax, ay, ctx->status, active);
+        } else {
+            const unsigned nb = blocks_for(p.nx, 256) < 64 ? blocks_for(p.nx, 256) : 64;
+            hipLaunchKernelGGL(k_alpha_scalar, dim3(nb), dim3(256), 0, ctx->stream, Us, (long)p.nx,
+                               p.system == ENOMR_ADVECTION ? SYS_ADVECTION : SYS_BURGERS, p.adv_speed, ax, active);
+        }
+    });
     HIP_TRY(hipGetLastError());
     return ENOMR_OK;
 }
@@ -155,10 +191,12 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
     if (p.system != ENOMR_EULER) {
         const int flux = p.system == ENOMR_ADVECTION ? SYS_ADVECTION : SYS_BURGERS;
         const int split = p.split == ENOMR_SPLIT_LF ? 1 : 0;
-        DISPATCH_R(p.order,
-                   hipLaunchKernelGGL((k_scalar_sweep<R, kTF1>), dim3(blocks_for(p.nx, kTF1 - 1)), dim3(kTF1), 0,
-                                      ctx->stream, Us, (long)p.nx, 1.0 / p.hx, flux, p.adv_speed, split, p.bc_x,
-                                      ax, so, idx, active));
+        timed(ctx, PROF_SWEEP_X, [&] {
+            DISPATCH_R(p.order,
+                       hipLaunchKernelGGL((k_scalar_sweep<R, kTF1>), dim3(blocks_for(p.nx, kTF1 - 1)), dim3(kTF1),
+                                          0, ctx->stream, Us, (long)p.nx, 1.0 / p.hx, flux, p.adv_speed, split,
+                                          p.bc_x, ax, so, idx, active));
+        });
         HIP_TRY(hipGetLastError());
         return ENOMR_OK;
     }
@@ -174,9 +212,11 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
         in.idx = idx;
         in.ih = 1.0 / p.hx;
         in.bc = p.bc_x;
-        DISPATCH_R(p.order,
-                   hipLaunchKernelGGL((k_euler_sweep<3, R, 0, kTF1, 1>), dim3(blocks_for(p.nx, kTF1 - 1), 1),
-                                      dim3(kTF1), 0, ctx->stream, in, so));
+        timed(ctx, PROF_SWEEP_X, [&] {
+            DISPATCH_R(p.order,
+                       hipLaunchKernelGGL((k_euler_sweep<3, R, 0, kTF1, 1>), dim3(blocks_for(p.nx, kTF1 - 1), 1),
+                                          dim3(kTF1), 0, ctx->stream, in, so));
+        });
         HIP_TRY(hipGetLastError());
         return ENOMR_OK;
     }
@@ -193,20 +233,24 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
     in.idx = idx;
     in.ih = 1.0 / p.hx;
     in.bc = p.bc_x;
-    DISPATCH_R(p.order,
-               hipLaunchKernelGGL((k_euler_sweep<4, R, 0, kTFx, kTLx>),
-                                  dim3(blocks_for(p.nx, kTFx - 1), blocks_for(p.ny, kTLx)), dim3(kTFx * kTLx), 0,
-                                  ctx->stream, in, sx));
+    timed(ctx, PROF_SWEEP_X, [&] {
+        DISPATCH_R(p.order,
+                   hipLaunchKernelGGL((k_euler_sweep<4, R, 0, kTFx, kTLx>),
+                                      dim3(blocks_for(p.nx, kTFx - 1), blocks_for(p.ny, kTLx)), dim3(kTFx * kTLx),
+                                      0, ctx->stream, in, sx));
+    });
     HIP_TRY(hipGetLastError());
     in.alpha = ay;
     in.idx = idx ? idx + (size_t)p.ny * (p.nx + 1) * 8 : nullptr;
     in.ih = 1.0 / p.hy;
     in.bc = p.bc_y;
     so.Lprev = Lx;
-    DISPATCH_R(p.order,
-               hipLaunchKernelGGL((k_euler_sweep<4, R, 1, kTFy, kTLy>),
-                                  dim3(blocks_for(p.ny, kTFy - 1), blocks_for(p.nx, kTLy)), dim3(kTFy * kTLy), 0,
-                                  ctx->stream, in, so));
+    timed(ctx, PROF_SWEEP_Y, [&] {
+        DISPATCH_R(p.order,
+                   hipLaunchKernelGGL((k_euler_sweep<4, R, 1, kTFy, kTLy>),
+                                      dim3(blocks_for(p.ny, kTFy - 1), blocks_for(p.nx, kTLy)), dim3(kTFy * kTLy),
+                                      0, ctx->stream, in, so));
+    });
     HIP_TRY(hipGetLastError());
     return ENOMR_OK;
 }
@@ -224,9 +268,11 @@ enomr_status launch_dt(enomr_ctx* ctx, const enomr_problem& p, double cfl, void*
     const Layout w = layout(p);
     const long nax = p.system == ENOMR_EULER ? p.ny : 1;
     const long nay = p.ndim == 2 ? p.nx : 0;
-    hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, at<double>(ws, w.ax), nax, at<double>(ws, w.ay),
-                       nay, cfl, 1.0 / p.hx, p.ndim == 2 ? 1.0 / p.hy : 0.0, t_end, dt, at<double>(ws, w.t),
-                       at<int>(ws, w.active), dt_log, step);
+    timed(ctx, PROF_AUX, [&] {
+        hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, at<double>(ws, w.ax), nax,
+                           at<double>(ws, w.ay), nay, cfl, 1.0 / p.hx, p.ndim == 2 ? 1.0 / p.hy : 0.0, t_end, dt,
+                           at<double>(ws, w.t), at<int>(ws, w.active), dt_log, step);
+    });
     HIP_TRY(hipGetLastError());
     return ENOMR_OK;
 }
@@ -310,8 +356,28 @@ enomr_status enomr_create(int device, void* hip_stream, enomr_ctx** out)
     static double ta[kPool][kMaxW], tb[kPool][kMaxW];
     static bool ready = generate_tables(ta, tb);
     (void)ready;
+    // window-aligned rows (centre at entry 8) and candidate -> pool maps
+    static double wa[2][kPool][kMaxW], wb[2][kPool][kMaxW];
+    static int cp[10][kPool];
+    for (int P = 0; P < kPool; ++P) {
+        const int m = pool_mn(P, 0), n = pool_mn(P, 1);
+        for (int i = 0; i < kMaxW; ++i) {
+            wa[0][P][i] = wb[0][P][i] = wa[1][P][i] = wb[1][P][i] = 0.0;
+        }
+        for (int l = -m; l <= n; ++l) {
+            wa[0][P][8 + l] = ta[P][l + m];   // f^+: offset l is window entry 8 + l
+            wb[0][P][8 + l] = tb[P][l + m];
+            wa[1][P][8 - l] = ta[P][l + m];   // f^-: offset l is window entry 8 - l
+            wb[1][P][8 - l] = tb[P][l + m];
+        }
+    }
+    for (int R = 0; R < 10; ++R)
+        for (int c = 0; c < kPool; ++c) cp[R][c] = (R >= 3 && c < n_cands(R)) ? cand_pool(R, c) : 0;
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_a), ta, sizeof(ta)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_b), tb, sizeof(tb)));
+    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_wa), wa, sizeof(wa)));
+    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_wb), wb, sizeof(wb)));
+    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_candpool), cp, sizeof(cp)));
     enomr_ctx* c = new enomr_ctx;
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -336,6 +402,11 @@ enomr_status enomr_destroy(enomr_ctx* ctx)
     if (!ctx) return ENOMR_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipFree(ctx->status);
+    for (auto& v : ctx->ev)
+        for (auto& pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
     delete ctx;
     return ENOMR_OK;
 }
@@ -431,6 +502,32 @@ enomr_status enomr_advance(enomr_ctx* ctx, const enomr_problem* prob, double* U,
         if (enomr_status st = launch_alpha(ctx, *prob, U, ws, act)) return st;
         if (enomr_status st = launch_dt(ctx, *prob, cfl, ws, dt, t_end, dt_log, (long)s)) return st;
         if (enomr_status st = rk3_step(ctx, *prob, U, dt, ws, nullptr, act, true)) return st;
+    }
+    return ENOMR_OK;
+}
+
+enomr_status enomr_profile_start(enomr_ctx* ctx)
+{
+    if (!ctx) return fail(ENOMR_EINVAL, "context is NULL");
+    ctx->prof = true;
+    for (auto& u : ctx->used) u = 0;
+    return ENOMR_OK;
+}
+
+enomr_status enomr_profile_stop(enomr_ctx* ctx, double* ms, int64_t* launches)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    ctx->prof = false;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (int c = 0; c < PROF_CLASSES; ++c) {
+        double tot = 0.0;
+        for (size_t i = 0; i < ctx->used[c]; ++i) {
+            float e = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&e, ctx->ev[c][i].first, ctx->ev[c][i].second));
+            tot += e;
+        }
+        if (ms) ms[c] = tot;
+        if (launches) launches[c] = (int64_t)ctx->used[c];
     }
     return ENOMR_OK;
 }

@@ -20,6 +20,16 @@ namespace enomr {
 extern __constant__ double c_a[kPool][kMaxW];
 extern __constant__ double c_b[kPool][kMaxW];
 
+// The same coefficients aligned to a 17-entry window centred at entry 8 and
+// zero outside the stencil: c_wa[s][P][i] multiplies window entry i for sign
+// s (0: +, 1: -).  A (2R-1)-entry window starts at entry 9-R.  A zero
+// coefficient adds an exact zero to an fma chain, so a padded chain rounds
+// like the stencil's own chain (up to the sign of a zero result).
+extern __constant__ double c_wa[2][kPool][kMaxW];
+extern __constant__ double c_wb[2][kPool][kMaxW];
+// Pool index of candidate c of the (2R-1)-point scheme: c_candpool[R][c].
+extern __constant__ int c_candpool[10][kPool];
+
 // Coefficient index of window entry i for stencil (m, n) and sign S.
 template <int R, int S, int m>
 __device__ constexpr int coef_index(int i)
@@ -93,6 +103,34 @@ __device__ __forceinline__ double select_from(const double (&w)[2 * R - 1], doub
     } else {
         return minmod_flux<R, S>(w, idx);
     }
+}
+
+// Steps 3.1/3.2 from candidate 1 on with a runtime loop over the padded
+// window-aligned rows (compact code for the rarely taken non-smooth path).
+template <int R, int S>
+__device__ __forceinline__ double select_tail_loop(const double (&w)[2 * R - 1], double is0, int& idx)
+{
+    constexpr int NC = n_cands(R);
+    constexpr int W = 2 * R - 1;
+    constexpr int off = 9 - R;
+    constexpr int s = S > 0 ? 0 : 1;
+#pragma unroll 1
+    for (int c = 1; c <= NC - 4; ++c) {
+        const int P = c_candpool[R][c];
+        const double* wb = &c_wb[s][P][off];
+        double acc = wb[0] * w[0];
+#pragma unroll
+        for (int i = 1; i < W; ++i) acc = fma(wb[i], w[i], acc);
+        if (fabs(acc) < is0) {
+            const double* wa = &c_wa[s][P][off];
+            double f = wa[0] * w[0];
+#pragma unroll
+            for (int i = 1; i < W; ++i) f = fma(wa[i], w[i], f);
+            idx = c;
+            return f;
+        }
+    }
+    return minmod_flux<R, S>(w, idx);
 }
 
 // The whole scalar reconstruction (Steps 1-3.2) of one window.

@@ -470,13 +470,19 @@ __global__ __launch_bounds__(TF* TL) void k_euler_sweep(SweepIn in, StageOut so)
         // field and sign the full-stencil indicator and flux and keeping the
         // five central values for IS0.
         constexpr int P0 = cand_pool(R, 0);
-        double isp[NV], flp[NV], ism[NV], flm[NV];
-        double cp[5][NV], cm[5][NV];   // centre +-2: + frame cells j-2..j+2, - frame j-1..j+3
+        double hp[NV], hm[NV];
+        unsigned fail = 0;
+        uint64_t idxw = 0;
+        // + sign: stream cells j-r+1 .. j+r-1 once, projecting G^+ onto every
+        // field and accumulating the full stencil's indicator and flux; the
+        // baseline indicator IS0 (Eq. Baseline_IS, centre j) is built as the
+        // centre cells go by.
+        {
+            double is[NV], fl[NV], a[NV], b[NV], cc[NV], isl[NV], is0[NV];
 #pragma unroll
-        for (int o = -R + 1; o <= R; ++o) {
-            const int lp = lpos(tl, jp + o);
-            if (o <= R - 1) {
+            for (int o = -R + 1; o <= R - 1; ++o) {
                 double G[NV], w[NV];
+                const int lp = lpos(tl, jp + o);
 #pragma unroll
                 for (int q = 0; q < NV; ++q) G[q] = sGp[q][lp];
                 project<NV>(e, G, w);
@@ -484,17 +490,45 @@ __global__ __launch_bounds__(TF* TL) void k_euler_sweep(SweepIn in, StageOut so)
 #pragma unroll
                 for (int q = 0; q < NV; ++q) {
                     if (o == -R + 1) {
-                        isp[q] = c_b[P0][ci] * w[q];
-                        flp[q] = c_a[P0][ci] * w[q];
+                        is[q] = c_b[P0][ci] * w[q];
+                        fl[q] = c_a[P0][ci] * w[q];
                     } else {
-                        isp[q] = fma(c_b[P0][ci], w[q], isp[q]);
-                        flp[q] = fma(c_a[P0][ci], w[q], flp[q]);
+                        is[q] = fma(c_b[P0][ci], w[q], is[q]);
+                        fl[q] = fma(c_a[P0][ci], w[q], fl[q]);
                     }
-                    if (o >= -2 && o <= 2) cp[o + 2][q] = w[q];
+                    if (o == -2) a[q] = w[q];
+                    if (o == -1) b[q] = w[q];
+                    if (o == 0) {
+                        const double f0 = w[q], fm1 = b[q], fm2 = a[q];
+                        cc[q] = f0;
+                        isl[q] = fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2));
+                    }
+                    if (o == 1) a[q] = w[q];
+                    if (o == 2) {
+                        const double f0 = cc[q], fp1 = a[q], fp2 = w[q];
+                        is0[q] = fmin(isl[q], fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2)));
+                    }
                 }
+                // Keep both chains advancing cell by cell: without this the
+                // compiler sinks them past the loop and holds every projected
+                // value in registers.
+#pragma unroll
+                for (int q = 0; q < NV; ++q) asm volatile("" : "+v"(is[q]), "+v"(fl[q]));
             }
-            if (o >= -R + 2) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                hp[q] = fl[q];
+                if (!(fabs(is[q]) < is0[q])) fail |= 1u << (2 * q);
+            }
+        }
+        // - sign: the mirror image, cells j-r+2 .. j+r, centre j+1 (its upwind
+        // side is j+2, j+3; its downwind side j, j-1).
+        {
+            double is[NV], fl[NV], a[NV], b[NV], cc[NV], isr[NV], is0[NV];
+#pragma unroll
+            for (int o = -R + 2; o <= R; ++o) {
                 double G[NV], w[NV];
+                const int lp = lpos(tl, jp + o);
 #pragma unroll
                 for (int q = 0; q < NV; ++q) G[q] = sGm[q][lp];
                 project<NV>(e, G, w);
@@ -502,37 +536,35 @@ __global__ __launch_bounds__(TF* TL) void k_euler_sweep(SweepIn in, StageOut so)
 #pragma unroll
                 for (int q = 0; q < NV; ++q) {
                     if (o == -R + 2) {
-                        ism[q] = c_b[P0][ci] * w[q];
-                        flm[q] = c_a[P0][ci] * w[q];
+                        is[q] = c_b[P0][ci] * w[q];
+                        fl[q] = c_a[P0][ci] * w[q];
                     } else {
-                        ism[q] = fma(c_b[P0][ci], w[q], ism[q]);
-                        flm[q] = fma(c_a[P0][ci], w[q], flm[q]);
+                        is[q] = fma(c_b[P0][ci], w[q], is[q]);
+                        fl[q] = fma(c_a[P0][ci], w[q], fl[q]);
                     }
-                    if (o >= -1 && o <= 3) cm[o + 1][q] = w[q];
+                    if (o == -1) a[q] = w[q];
+                    if (o == 0) b[q] = w[q];
+                    if (o == 1) {
+                        const double f0 = w[q], fp1 = b[q], fp2 = a[q];
+                        cc[q] = f0;
+                        isr[q] = fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2));
+                    }
+                    if (o == 2) a[q] = w[q];
+                    if (o == 3) {
+                        const double f0 = cc[q], fm1 = a[q], fm2 = w[q];
+                        is0[q] = fmin(fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2)), isr[q]);
+                    }
                 }
-            }
-        }
-
-        double hp[NV], hm[NV];
-        unsigned fail = 0;
-        uint64_t idxw = 0;
+                // Keep both chains advancing cell by cell: without this the
+                // compiler sinks them past the loop and holds every projected
+                // value in registers.
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            // + frame: centre cp[2]; left neighbours cp[1], cp[0]; right cp[3], cp[4]
-            {
-                const double f0 = cp[2][q], fm1 = cp[1][q], fm2 = cp[0][q], fp1 = cp[3][q], fp2 = cp[4][q];
-                const double is0 = fmin(fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2)),
-                                        fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2)));
-                hp[q] = flp[q];
-                if (!(fabs(isp[q]) < is0)) fail |= 1u << (2 * q);
+                for (int q = 0; q < NV; ++q) asm volatile("" : "+v"(is[q]), "+v"(fl[q]));
             }
-            // - frame: centre cell j+1 = cm[2]; its upwind side is j+2, j+3
-            {
-                const double f0 = cm[2][q], fm1 = cm[3][q], fm2 = cm[4][q], fp1 = cm[1][q], fp2 = cm[0][q];
-                const double is0 = fmin(fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2)),
-                                        fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2)));
-                hm[q] = flm[q];
-                if (!(fabs(ism[q]) < is0)) fail |= 1u << (2 * q + 1);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                hm[q] = fl[q];
+                if (!(fabs(is[q]) < is0[q])) fail |= 1u << (2 * q + 1);
             }
         }
 
@@ -556,7 +588,7 @@ __global__ __launch_bounds__(TF* TL) void k_euler_sweep(SweepIn in, StageOut so)
                         for (int c = 0; c < NV; ++c) G[c] = sGp[c][lp];
                         w[i] = row_chain<NV>(r, G);
                     }
-                    res = select_from<R, +1, 1>(w, baseline_is<R, +1>(w), id);
+                    res = select_tail_loop<R, +1>(w, baseline_is<R, +1>(w), id);
                 } else {
 #pragma unroll
                     for (int i = 0; i < W; ++i) {
@@ -566,7 +598,7 @@ __global__ __launch_bounds__(TF* TL) void k_euler_sweep(SweepIn in, StageOut so)
                         for (int c = 0; c < NV; ++c) G[c] = sGm[c][lp];
                         w[i] = row_chain<NV>(r, G);
                     }
-                    res = select_from<R, -1, 1>(w, baseline_is<R, -1>(w), id);
+                    res = select_tail_loop<R, -1>(w, baseline_is<R, -1>(w), id);
                 }
 #pragma unroll
                 for (int t = 0; t < NV; ++t) {
