@@ -149,7 +149,7 @@ void timed(enomr_ctx* ctx, int cls, F&& launch)
 // Tile shapes (faces per line x lines per block).
 constexpr int kTF1 = 64;                  // 1D lines
 constexpr int kTFx = 64, kTLx = 4;        // 2D x sweep
-constexpr int kTFy = 32, kTLy = 8;        // 2D y sweep
+constexpr int kTFy = 64, kTLy = 4;        // 2D y sweep
 
 // Alphas of every line of `Us` into ws (zeroed first).
 enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* Us, void* ws,

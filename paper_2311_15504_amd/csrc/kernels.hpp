@@ -389,7 +389,7 @@ struct SweepIn {
 // are columns (y faces), evaluated on the permuted state (rho, n, m, E) so the
 // same x-normal formulas apply.
 template <int NV, int R, int DIR, int TF, int TL>
-__global__ __launch_bounds__(TF* TL) void k_euler_sweep(SweepIn in, StageOut so)
+__global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut so)
 {
     if (in.active && *in.active == 0) return;
     constexpr int NT = TF * TL;
@@ -518,7 +518,13 @@ __global__ __launch_bounds__(TF* TL) void k_euler_sweep(SweepIn in, StageOut so)
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 hp[q] = fl[q];
-                if (!(fabs(is[q]) < is0[q])) fail |= 1u << (2 * q);
+                if (is0[q] == 0.0) {
+                    // a flat side: no IS can be below 0, minmod gives the centre value
+                    hp[q] = cc[q] + 0.5 * 0.0;
+                    idxw |= (uint64_t)(n_cands(R) - 1) << (8 * (2 * q));
+                } else if (!(fabs(is[q]) < is0[q])) {
+                    fail |= 1u << (2 * q);
+                }
             }
         }
         // - sign: the mirror image, cells j-r+2 .. j+r, centre j+1 (its upwind
@@ -564,7 +570,12 @@ __global__ __launch_bounds__(TF* TL) void k_euler_sweep(SweepIn in, StageOut so)
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 hm[q] = fl[q];
-                if (!(fabs(is[q]) < is0[q])) fail |= 1u << (2 * q + 1);
+                if (is0[q] == 0.0) {
+                    hm[q] = cc[q] + 0.5 * 0.0;
+                    idxw |= (uint64_t)(n_cands(R) - 1) << (8 * (2 * q + 1));
+                } else if (!(fabs(is[q]) < is0[q])) {
+                    fail |= 1u << (2 * q + 1);
+                }
             }
         }
 
