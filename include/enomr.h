@@ -165,6 +165,32 @@ enomr_status enomr_check(enomr_ctx *ctx);
 enomr_status enomr_profile_start(enomr_ctx *ctx);
 enomr_status enomr_profile_stop(enomr_ctx *ctx, double *ms, int64_t *launches);
 
+/*
+ * Batched persistent execution: many independent 1D Euler problems (uneven
+ * lengths and orders) advanced together by one persistent launch replayed
+ * from a hipGraph.  Each problem advances with its own per-stage alpha and
+ * CFL time step exactly as enomr_advance() would advance it alone, and its
+ * result is bitwise equal to that run.
+ *
+ * enomr_batch_create: probs[nprob] (ndim 1, ENOMR_EULER, any order 5..17),
+ * U[nprob] device pointers to the problems' [3][nx] states, bound to the batch
+ * for its lifetime and advanced in place.  The batch allocates its own stage
+ * workspace (2 states per problem).  autotune != 0 times one step of the
+ * whole batch on scratch copies for each tile width (64, 128, 256 faces) and
+ * keeps the fastest; otherwise 128.  The work queue hands out problems
+ * longest first.
+ * enomr_batch_advance: nsteps SSP-RK3 steps of every problem at CFL `cfl`.
+ * enomr_batch_info: chosen tile width, workgroups, and the autotune times (ms,
+ * for widths 64/128/256; zeros without autotune).  Any pointer may be NULL.
+ */
+typedef struct enomr_batch enomr_batch;
+enomr_status enomr_batch_create(enomr_ctx *ctx, int32_t nprob, const enomr_problem *probs, double *const *U,
+                                int autotune, enomr_batch **out);
+enomr_status enomr_batch_advance(enomr_batch *batch, double cfl, int64_t nsteps);
+enomr_status enomr_batch_info(const enomr_batch *batch, int32_t *tile_faces, int32_t *workgroups,
+                              double *tune_ms);
+enomr_status enomr_batch_destroy(enomr_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -95,6 +95,10 @@ def lib():
             "enomr_check": ([_vp], st),
             "enomr_profile_start": ([_vp], st),
             "enomr_profile_stop": ([_vp, _vp, _vp], st),
+            "enomr_batch_create": ([_vp, ctypes.c_int32, P, _vp, ctypes.c_int, ctypes.POINTER(_vp)], st),
+            "enomr_batch_advance": ([_vp, ctypes.c_double, ctypes.c_int64], st),
+            "enomr_batch_info": ([_vp, _vp, _vp, _vp], st),
+            "enomr_batch_destroy": ([_vp], st),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -228,3 +232,49 @@ class Context:
         self._sync_stream()
         _call("enomr_profile_stop", self.handle, ctypes.cast(ms, _vp), ctypes.cast(n, _vp))
         return {k: (ms[i], n[i]) for i, k in enumerate(("sweep_x", "sweep_y", "aux"))}
+
+
+class Batch:
+    """Many independent 1D Euler problems advanced by one persistent launch
+    (enomr_batch_*).  `states` are the problems' [3][n] float64 CUDA tensors;
+    they stay bound to the batch and are advanced in place."""
+
+    def __init__(self, ctx, problems, states, autotune=True):
+        if len(problems) != len(states) or not problems:
+            raise ValueError("one state per problem")
+        for p, U in zip(problems, states):
+            ctx._check_state(p, U)
+        self.ctx = ctx
+        self.states = list(states)
+        n = len(problems)
+        arr = (Problem * n)(*problems)
+        ptrs = (ctypes.c_void_p * n)(*[U.data_ptr() for U in states])
+        h = _vp()
+        ctx._sync_stream()
+        _call("enomr_batch_create", ctx.handle, n, arr, ctypes.cast(ptrs, _vp), 1 if autotune else 0,
+              ctypes.byref(h))
+        self.handle = h
+
+    def advance(self, cfl, nsteps):
+        self.ctx._sync_stream()
+        _call("enomr_batch_advance", self.handle, cfl, nsteps)
+
+    def info(self):
+        tf = ctypes.c_int32()
+        nb = ctypes.c_int32()
+        ms = (ctypes.c_double * 3)()
+        _call("enomr_batch_info", self.handle, ctypes.cast(ctypes.byref(tf), _vp), ctypes.cast(ctypes.byref(nb), _vp),
+              ctypes.cast(ms, _vp))
+        return {"tile_faces": tf.value, "workgroups": nb.value, "tune_ms": list(ms)}
+
+    def close(self):
+        if self.handle:
+            lib().enomr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -31,6 +32,22 @@ struct enomr_ctx {
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[PROF_CLASSES];
     size_t used[PROF_CLASSES] = {0, 0, 0};
+};
+
+struct enomr_batch {
+    enomr_ctx* ctx = nullptr;
+    int nprob = 0;
+    int tf = 128;                  // faces per tile (autotuned)
+    unsigned nblocks = 0;          // persistent workgroups
+    BatchProb* d_probs = nullptr;
+    int* d_order = nullptr;
+    int* d_queue = nullptr;
+    BatchParams* d_params = nullptr;
+    double* d_ws = nullptr;        // stage states of every problem
+    hipStream_t cap = nullptr;     // capture stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double tune_ms[3] = {0, 0, 0}; // one-step times of the tile widths 64, 128, 256
 };
 
 namespace {
@@ -542,6 +559,211 @@ enomr_status enomr_check(enomr_ctx* ctx)
         HIP_TRY(hipMemset(ctx->status, 0, sizeof(unsigned)));
         return fail(ENOMR_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN) met on the device");
     }
+    return ENOMR_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched persistent execution
+// ---------------------------------------------------------------------------
+
+namespace {
+
+const int kBatchTF[3] = {64, 128, 256};
+
+hipError_t launch_batch(enomr_batch* b, int tf, const BatchProb* probs, hipStream_t st)
+{
+    switch (tf) {
+    case 64:
+        hipLaunchKernelGGL(k_batch_euler1d<64>, dim3(b->nblocks), dim3(64), 0, st, probs, b->d_order, b->nprob,
+                           b->d_queue, b->d_params, b->ctx->status);
+        break;
+    case 128:
+        hipLaunchKernelGGL(k_batch_euler1d<128>, dim3(b->nblocks), dim3(128), 0, st, probs, b->d_order, b->nprob,
+                           b->d_queue, b->d_params, b->ctx->status);
+        break;
+    default:
+        hipLaunchKernelGGL(k_batch_euler1d<256>, dim3(b->nblocks), dim3(256), 0, st, probs, b->d_order, b->nprob,
+                           b->d_queue, b->d_params, b->ctx->status);
+        break;
+    }
+    return hipGetLastError();
+}
+
+unsigned batch_blocks(int tf, int nprob)
+{
+    int per_cu = 0, ncu = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = hipErrorInvalidValue;
+    if (tf == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_euler1d<64>, 64, 0);
+    else if (tf == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_euler1d<128>, 128, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_euler1d<256>, 256, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    if (ncu < 1) ncu = 1;
+    long nb = (long)per_cu * ncu;
+    if (nb > nprob) nb = nprob;
+    return (unsigned)(nb < 1 ? 1 : nb);
+}
+
+void batch_free(enomr_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    (void)hipFree(b->d_probs);
+    (void)hipFree(b->d_order);
+    (void)hipFree(b->d_queue);
+    (void)hipFree(b->d_params);
+    (void)hipFree(b->d_ws);
+    delete b;
+}
+
+}  // namespace
+
+enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_problem* probs, double* const* U,
+                                int autotune, enomr_batch** out)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    if (!out || !probs || !U || nprob < 1) return fail(ENOMR_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    std::vector<BatchProb> hp(nprob);
+    std::vector<double> cost(nprob);
+    size_t total = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const enomr_problem& p = probs[i];
+        if (enomr_status st = check_problem(&p)) return st;
+        if (p.system != ENOMR_EULER || p.ndim != 1)
+            return fail(ENOMR_EINVAL, "batched problems must be 1D Euler");
+        if (!U[i]) return fail(ENOMR_EINVAL, "NULL state in batch");
+        total += align_up(sizeof(double) * 3 * (size_t)p.nx) * 2;
+    }
+    enomr_batch* b = new enomr_batch;
+    b->ctx = ctx;
+    b->nprob = nprob;
+    auto bail = [&](enomr_status st, const std::string& m) {
+        batch_free(b);
+        return fail(st, m);
+    };
+    if (hipMalloc(&b->d_ws, total) != hipSuccess) return bail(ENOMR_ENOMEM, "cannot allocate batch workspace");
+    size_t off = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const enomr_problem& p = probs[i];
+        const size_t sz = align_up(sizeof(double) * 3 * (size_t)p.nx);
+        BatchProb& q = hp[i];
+        q.U = U[i];
+        q.U1 = reinterpret_cast<double*>(reinterpret_cast<char*>(b->d_ws) + off);
+        q.U2 = reinterpret_cast<double*>(reinterpret_cast<char*>(b->d_ws) + off + sz);
+        off += 2 * sz;
+        q.n = p.nx;
+        q.ih = 1.0 / p.hx;
+        q.gamma = p.gamma;
+        q.R = (p.order + 1) / 2;
+        q.bc = p.bc_x;
+        cost[i] = (double)p.nx * (double)(q.R + 3);
+    }
+    // longest first: the work queue then hands out problems in LPT order
+    std::vector<int> order(nprob);
+    for (int i = 0; i < nprob; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    if (hipMalloc(&b->d_probs, sizeof(BatchProb) * nprob) != hipSuccess ||
+        hipMalloc(&b->d_order, sizeof(int) * nprob) != hipSuccess || hipMalloc(&b->d_queue, sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->d_params, sizeof(BatchParams)) != hipSuccess)
+        return bail(ENOMR_ENOMEM, "cannot allocate batch descriptors");
+    if (hipMemcpy(b->d_probs, hp.data(), sizeof(BatchProb) * nprob, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_order, order.data(), sizeof(int) * nprob, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(ENOMR_EHIP, "cannot upload batch descriptors");
+
+    // Autotune the tile width: one step of the whole batch on scratch copies of
+    // the states, per width; the fastest wins.
+    b->tf = 128;
+    if (autotune) {
+        size_t state_bytes = 0;
+        for (int i = 0; i < nprob; ++i) state_bytes += align_up(sizeof(double) * 3 * (size_t)probs[i].nx);
+        double* scratch = nullptr;
+        BatchProb* d_tune = nullptr;
+        if (hipMalloc(&scratch, state_bytes) != hipSuccess || hipMalloc(&d_tune, sizeof(BatchProb) * nprob) != hipSuccess) {
+            (void)hipFree(scratch);
+            return bail(ENOMR_ENOMEM, "cannot allocate autotune scratch");
+        }
+        std::vector<BatchProb> tp = hp;
+        size_t so = 0;
+        for (int i = 0; i < nprob; ++i) {
+            tp[i].U = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) + so);
+            so += align_up(sizeof(double) * 3 * (size_t)probs[i].nx);
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool ok = hipMemcpy(d_tune, tp.data(), sizeof(BatchProb) * nprob, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+        double best = 1e300;
+        for (int t = 0; ok && t < 3; ++t) {
+            const int tf = kBatchTF[t];
+            for (int i = 0; i < nprob && ok; ++i)
+                ok = hipMemcpyAsync(tp[i].U, U[i], sizeof(double) * 3 * (size_t)probs[i].nx, hipMemcpyDeviceToDevice,
+                                    ctx->stream) == hipSuccess;
+            b->nblocks = batch_blocks(tf, nprob);
+            hipLaunchKernelGGL(k_set_batch_params, dim3(1), dim3(64), 0, ctx->stream, b->d_params, 0.5, 1L, b->d_queue);
+            ok = ok && hipEventRecord(e0, ctx->stream) == hipSuccess;
+            ok = ok && launch_batch(b, tf, d_tune, ctx->stream) == hipSuccess;
+            ok = ok && hipEventRecord(e1, ctx->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.0f;
+            ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            b->tune_ms[t] = ms;
+            if (ok && ms < best) {
+                best = ms;
+                b->tf = tf;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(d_tune);
+        (void)hipFree(scratch);
+        if (!ok) return bail(ENOMR_EHIP, "autotune failed");
+        // the autotune steps may have latched a status; keep it for enomr_check
+    }
+    b->nblocks = batch_blocks(b->tf, nprob);
+
+    // Capture the persistent launch into a graph, replayed by every advance.
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(ENOMR_EHIP, "cannot create capture stream");
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bail(ENOMR_EHIP, "cannot begin capture");
+    hipError_t le = launch_batch(b, b->tf, b->d_probs, b->cap);
+    hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
+    if (le != hipSuccess || ce != hipSuccess) return bail(ENOMR_EHIP, "capture of the batch launch failed");
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(ENOMR_EHIP, "cannot instantiate the batch graph");
+    *out = b;
+    return ENOMR_OK;
+}
+
+enomr_status enomr_batch_advance(enomr_batch* b, double cfl, int64_t nsteps)
+{
+    if (!b) return fail(ENOMR_EINVAL, "batch is NULL");
+    if (enomr_status st = check_ctx(b->ctx)) return st;
+    if (!(cfl > 0.0) || nsteps < 0) return fail(ENOMR_EINVAL, "bad cfl or nsteps");
+    hipLaunchKernelGGL(k_set_batch_params, dim3(1), dim3(64), 0, b->ctx->stream, b->d_params, cfl, (long)nsteps,
+                       b->d_queue);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipGraphLaunch(b->exec, b->ctx->stream));
+    return ENOMR_OK;
+}
+
+enomr_status enomr_batch_info(const enomr_batch* b, int32_t* tile_faces, int32_t* workgroups, double* tune_ms)
+{
+    if (!b) return fail(ENOMR_EINVAL, "batch is NULL");
+    if (tile_faces) *tile_faces = b->tf;
+    if (workgroups) *workgroups = (int32_t)b->nblocks;
+    if (tune_ms)
+        for (int i = 0; i < 3; ++i) tune_ms[i] = b->tune_ms[i];
+    return ENOMR_OK;
+}
+
+enomr_status enomr_batch_destroy(enomr_batch* b)
+{
+    if (!b) return ENOMR_OK;
+    (void)hipSetDevice(b->ctx->device);
+    batch_free(b);
     return ENOMR_OK;
 }
 

@@ -385,29 +385,34 @@ struct SweepIn {
     int bc;
 };
 
-// Characteristic ENO-MR sweep.  DIR 0: lines are rows (x faces); DIR 1: lines
-// are columns (y faces), evaluated on the permuted state (rho, n, m, E) so the
-// same x-normal formulas apply.
-template <int NV, int R, int DIR, int TF, int TL>
-__global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut so)
+// LDS of one sweep tile: split fluxes and Roe inputs of NCELL staged cells
+// (structure of arrays) and the NFACE face fluxes.
+template <int NV, int NCELL, int NFACE>
+struct SweepLds {
+    double Gp[NV][NCELL];
+    double Gm[NV][NCELL];
+    double Sq[NCELL], Un[NCELL], H[NCELL];
+    double Ut[NV == 4 ? NCELL : 1];
+    double F[NV][NFACE];
+};
+
+// One tile of the characteristic ENO-MR sweep: lines line0 .. line0+TL-1,
+// faces c0 .. c0+TF-1 (cells c0 .. c0+TF-2).  DIR 0: lines are rows (x faces);
+// DIR 1: lines are columns (y faces), evaluated on the permuted state
+// (rho, n, m, E) so that the same x-normal formulas apply.  NCL >= TF+2R-1 is
+// the LDS stride per line.  All threads of the block must call it.
+template <int NV, int R, int DIR, int TF, int TL, int NCL>
+__device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so, long line0, long c0,
+                                           SweepLds<NV, NCL * TL, TF * TL>& sm)
 {
-    if (in.active && *in.active == 0) return;
     constexpr int NT = TF * TL;
     constexpr int TC = TF - 1;
-    constexpr int NCL = TF + 2 * R - 1;
-    constexpr int NCELL = NCL * TL;
+    constexpr int NCU = TF + 2 * R - 1;   // cells staged per line
     constexpr int W = 2 * R - 1;
-    __shared__ double sGp[NV][NCELL];
-    __shared__ double sGm[NV][NCELL];
-    __shared__ double sSq[NCELL], sUn[NCELL], sH[NCELL];
-    __shared__ double sUt[NV == 4 ? NCELL : 1];
-    __shared__ double sF[NV][TF * TL];
-
+    static_assert(NCU <= NCL, "tile stride too small");
     const long nx = in.nx, ny = in.ny, plane = nx * ny;
     const long nlines = DIR == 0 ? ny : nx;
     const long n = DIR == 0 ? nx : ny;
-    const long line0 = (long)blockIdx.y * TL;
-    const long c0 = (long)blockIdx.x * TC;
     const double gamma = in.gamma, gm1 = gamma - 1.0;
     // normal-frame component q -> global variable
     auto gvar = [](int q) { return (DIR == 1 && NV == 4) ? (q == 1 ? 2 : (q == 2 ? 1 : q)) : q; };
@@ -415,9 +420,9 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
     auto gidx = [nx](long line, long cell) { return DIR == 0 ? line * nx + cell : cell * nx + line; };
 
     // ---- stage the tile: primitives, LF split G = (F +- alpha U)/2, Roe inputs
-    for (int e = threadIdx.x; e < NCELL; e += NT) {
-        const int line = DIR == 0 ? e / NCL : e % TL;
-        const int cell = DIR == 0 ? e % NCL : e / TL;
+    for (int e = threadIdx.x; e < NCU * TL; e += NT) {
+        const int line = DIR == 0 ? e / NCU : e % TL;
+        const int cell = DIR == 0 ? e % NCU : e / TL;
         const long gl = line0 + line;
         if (gl >= nlines) continue;
         const long g = gidx(gl, map_cell(c0 - R + cell, n, in.bc));
@@ -442,13 +447,13 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const double t = al * Uc[q];
-            sGp[q][lp] = 0.5 * (F[q] + t);
-            sGm[q][lp] = 0.5 * (F[q] - t);
+            sm.Gp[q][lp] = 0.5 * (F[q] + t);
+            sm.Gm[q][lp] = 0.5 * (F[q] - t);
         }
-        sSq[lp] = sqrt(rho);
-        sUn[lp] = un;
-        if constexpr (NV == 4) sUt[lp] = ut;
-        sH[lp] = (E + p) * ir;
+        sm.Sq[lp] = sqrt(rho);
+        sm.Un[lp] = un;
+        if constexpr (NV == 4) sm.Ut[lp] = ut;
+        sm.H[lp] = (E + p) * ir;
     }
     __syncthreads();
 
@@ -462,8 +467,8 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
         const int jp = tf + R - 1;   // left cell of the face in the tile
         const int pl = lpos(tl, jp), pr = lpos(tl, jp + 1);
         Eig e;
-        const bool ok = roe_eigen<NV>(sSq[pl], sUn[pl], NV == 4 ? sUt[pl] : 0.0, sH[pl], sSq[pr], sUn[pr],
-                                      NV == 4 ? sUt[pr] : 0.0, sH[pr], gm1, e);
+        const bool ok = roe_eigen<NV>(sm.Sq[pl], sm.Un[pl], NV == 4 ? sm.Ut[pl] : 0.0, sm.H[pl], sm.Sq[pr], sm.Un[pr],
+                                      NV == 4 ? sm.Ut[pr] : 0.0, sm.H[pr], gm1, e);
         if (!ok) flag_nonphysical(in.status);
 
         // ---- smooth path: stream the window once, accumulating for every
@@ -484,7 +489,7 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
                 double G[NV], w[NV];
                 const int lp = lpos(tl, jp + o);
 #pragma unroll
-                for (int q = 0; q < NV; ++q) G[q] = sGp[q][lp];
+                for (int q = 0; q < NV; ++q) G[q] = sm.Gp[q][lp];
                 project<NV>(e, G, w);
                 const int ci = o + (R - 1);
 #pragma unroll
@@ -536,7 +541,7 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
                 double G[NV], w[NV];
                 const int lp = lpos(tl, jp + o);
 #pragma unroll
-                for (int q = 0; q < NV; ++q) G[q] = sGm[q][lp];
+                for (int q = 0; q < NV; ++q) G[q] = sm.Gm[q][lp];
                 project<NV>(e, G, w);
                 const int ci = R - o;
 #pragma unroll
@@ -596,7 +601,7 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
                         const int lp = lpos(tl, jp - (R - 1) + i);
                         double G[NV];
 #pragma unroll
-                        for (int c = 0; c < NV; ++c) G[c] = sGp[c][lp];
+                        for (int c = 0; c < NV; ++c) G[c] = sm.Gp[c][lp];
                         w[i] = row_chain<NV>(r, G);
                     }
                     res = select_tail_loop<R, +1>(w, baseline_is<R, +1>(w), id);
@@ -606,7 +611,7 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
                         const int lp = lpos(tl, jp - (R - 2) + i);
                         double G[NV];
 #pragma unroll
-                        for (int c = 0; c < NV; ++c) G[c] = sGm[c][lp];
+                        for (int c = 0; c < NV; ++c) G[c] = sm.Gm[c][lp];
                         w[i] = row_chain<NV>(r, G);
                     }
                     res = select_tail_loop<R, -1>(w, baseline_is<R, -1>(w), id);
@@ -627,7 +632,7 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
         for (int q = 0; q < NV; ++q) wh[q] = hp[q] + hm[q];
         back_project<NV>(e, wh, Fh);
 #pragma unroll
-        for (int q = 0; q < NV; ++q) sF[q][tl * TF + tf] = Fh[q];
+        for (int q = 0; q < NV; ++q) sm.F[q][tl * TF + tf] = Fh[q];
 
         if (in.idx) {
             uint8_t* dst = DIR == 0 ? in.idx + ((gl * (n + 1) + face) * NV) * 2
@@ -646,10 +651,149 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const int v = gvar(q);
-            double L = -((sF[q][tl * TF + tf + 1] - sF[q][tl * TF + tf]) * in.ih);
+            double L = -((sm.F[q][tl * TF + tf + 1] - sm.F[q][tl * TF + tf]) * in.ih);
             if (so.Lprev) L = so.Lprev[v * plane + g] + L;
             if (so.stage == 0) so.out[v * plane + g] = L;
             else so.out[v * plane + g] = rk_combine(so.stage, so.Un[v * plane + g], in.Us[v * plane + g], L, dt);
+        }
+    }
+}
+
+template <int NV, int R, int DIR, int TF, int TL>
+__global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut so)
+{
+    if (in.active && *in.active == 0) return;
+    constexpr int NCL = TF + 2 * R - 1;
+    __shared__ SweepLds<NV, NCL * TL, TF * TL> lds;
+    sweep_tile<NV, R, DIR, TF, TL, NCL>(in, so, (long)blockIdx.y * TL, (long)blockIdx.x * (TF - 1), lds);
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent execution: many independent 1D Euler problems of uneven
+// lengths and orders in one launch.  Each workgroup takes whole problems from
+// an atomic queue (host-sorted by decreasing cost) and advances one problem
+// through all its steps: per stage a workgroup reduction gives the line's
+// alpha (and dt at the first stage), then the line is swept tile by tile with
+// the same tile code as the single-problem kernels, so every problem's result
+// equals its single-problem run bit for bit.
+// ---------------------------------------------------------------------------
+
+struct BatchProb {
+    double* U;       // [3][n] state, advanced in place
+    double* U1;      // stage states (workspace)
+    double* U2;
+    long n;
+    double ih;
+    double gamma;
+    int R;           // (order + 1) / 2
+    int bc;
+};
+
+struct BatchParams {
+    double cfl;
+    long nsteps;
+};
+
+__global__ void k_set_batch_params(BatchParams* p, double cfl, long nsteps, int* queue)
+{
+    if (threadIdx.x == 0) {
+        p->cfl = cfl;
+        p->nsteps = nsteps;
+        *queue = 0;
+    }
+}
+
+// Largest |u| + c over a 1D Euler line, by every thread of the workgroup (NT
+// threads); all threads get the result.
+template <int NT>
+__device__ __forceinline__ double block_max_speed(const double* __restrict__ U, long n, double gamma,
+                                                  unsigned* status, double* red)
+{
+    const double gm1 = gamma - 1.0;
+    double m = 0.0;
+    for (long i = threadIdx.x; i < n; i += NT) {
+        const double rho = U[i], mo = U[n + i], E = U[2 * n + i];
+        const double ir = 1.0 / rho;
+        const double u = mo * ir;
+        const double ke = 0.5 * (mo * u);
+        const double p = gm1 * (E - ke);
+        if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(mo)) flag_nonphysical(status);
+        m = fmax(m, fabs(u) + sqrt((gamma * p) * ir));
+    }
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) r = fmax(r, red[w]);
+    __syncthreads();
+    return r;
+}
+
+template <int R, int TF>
+__device__ __forceinline__ void run_problem(const BatchProb& P, const BatchParams& prm, unsigned* status,
+                                            char* lds_raw, double* red, double* s_alpha, double* s_dt)
+{
+    using Lds = SweepLds<3, TF + 17, TF>;
+    Lds& sm = *reinterpret_cast<Lds*>(lds_raw);
+    for (long step = 0; step < prm.nsteps; ++step) {
+        for (int stage = 1; stage <= 3; ++stage) {
+            const double* Us = stage == 1 ? P.U : (stage == 2 ? P.U1 : P.U2);
+            double* out = stage == 1 ? P.U1 : (stage == 2 ? P.U2 : P.U);
+            const double a = block_max_speed<TF>(Us, P.n, P.gamma, status, red);
+            if (threadIdx.x == 0) {
+                *s_alpha = a;
+                if (stage == 1) *s_dt = prm.cfl / (a * P.ih);
+            }
+            __syncthreads();
+            SweepIn in;
+            in.Us = Us;
+            in.alpha = s_alpha;
+            in.status = status;
+            in.idx = nullptr;
+            in.active = nullptr;
+            in.nx = P.n;
+            in.ny = 1;
+            in.ih = P.ih;
+            in.gamma = P.gamma;
+            in.bc = P.bc;
+            StageOut so;
+            so.Un = P.U;
+            so.Lprev = nullptr;
+            so.out = out;
+            so.dt = s_dt;
+            so.stage = stage;
+            for (long c0 = 0; c0 < P.n; c0 += TF - 1) sweep_tile<3, R, 0, TF, 1, TF + 17>(in, so, 0, c0, sm);
+            __syncthreads();
+        }
+    }
+}
+
+template <int TF>
+__global__ __launch_bounds__(TF, 4) void k_batch_euler1d(const BatchProb* __restrict__ probs,
+                                                         const int* __restrict__ order, int nprob, int* queue,
+                                                         const BatchParams* prm, unsigned* status)
+{
+    __shared__ __align__(16) char lds_raw[sizeof(SweepLds<3, (TF + 17), TF>)];
+    __shared__ double red[TF / 64];
+    __shared__ double s_alpha, s_dt;
+    __shared__ int s_k;
+    const BatchParams P = *prm;
+    for (;;) {
+        if (threadIdx.x == 0) s_k = atomicAdd(queue, 1);
+        __syncthreads();
+        const int k = s_k;
+        __syncthreads();
+        if (k >= nprob) return;   // the whole workgroup leaves together
+        const BatchProb pr = probs[order[k]];
+        switch (pr.R) {
+        case 3: run_problem<3, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
+        case 4: run_problem<4, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
+        case 5: run_problem<5, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
+        case 6: run_problem<6, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
+        case 7: run_problem<7, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
+        case 8: run_problem<8, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
+        default: run_problem<9, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
         }
     }
 }

@@ -1,0 +1,83 @@
+"""Batched persistent execution (one hipGraph-replayed launch for many 1D
+Euler problems of uneven sizes and orders): each problem equals its
+single-problem run bit for bit, and the oracle to the final-time tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_15504_amd as enomr
+    c = enomr.Context(0)
+    yield c
+    c.close()
+
+
+def _problems(nprob, seed):
+    import paper_2311_15504_amd as enomr
+    rng = np.random.default_rng(seed)
+    probs, data = [], []
+    for i in range(nprob):
+        order = int(rng.choice([5, 7, 9, 11, 13, 15, 17]))
+        n = int(rng.integers(40, 700))
+        bc = enomr.OUTFLOW if i % 5 else enomr.PERIODIC
+        if bc == enomr.PERIODIC:
+            _, h, U = workloads.euler1d_smooth_periodic(seed * 1000 + i, n)
+        else:
+            _, h, U = workloads.euler1d_riemann_perturbed(seed * 1000 + i, n)
+        probs.append(enomr.Problem.euler1d(n, h, order, bc=bc))
+        data.append(U)
+    return probs, data
+
+
+def test_batch_equals_single_problem_runs_bitwise(ctx):
+    import torch
+    import paper_2311_15504_amd as enomr
+    probs, data = _problems(37, 1)
+    states = [torch.from_numpy(U).cuda() for U in data]
+    batch = enomr.Batch(ctx, probs, states, autotune=True)
+    info = batch.info()
+    assert info["tile_faces"] in (64, 128, 256) and info["workgroups"] >= 1
+    assert all(t > 0 for t in info["tune_ms"])
+    batch.advance(0.5, 12)
+    batch.advance(0.5, 3)                    # resuming continues the same run
+    ctx.check()
+    for p, U0, Ub in zip(probs, data, states):
+        Us = torch.from_numpy(U0).cuda()
+        ctx.advance(p, Us, 0.5, 15)
+        ctx.check()
+        assert torch.equal(Ub, Us), (p.nx, p.order)
+    batch.close()
+
+
+def test_batch_matches_oracle(ctx):
+    import torch
+    import paper_2311_15504_amd as enomr
+    probs, data = _problems(6, 2)
+    states = [torch.from_numpy(U).cuda() for U in data]
+    batch = enomr.Batch(ctx, probs, states, autotune=False)
+    assert batch.info()["tile_faces"] == 128
+    batch.advance(0.5, 10)
+    ctx.check()
+    for p, U0, Ub in zip(probs, data, states):
+        ref, _ = oracle.euler1d_run(p.order, U0, p.hx, 10, cfl=0.5, bc=p.bc_x)
+        got = Ub.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+    batch.close()
+
+
+def test_batch_rejects_bad_problems(ctx):
+    import torch
+    import paper_2311_15504_amd as enomr
+    (x, y, hx, hy), U2 = workloads.euler2d_quadrants_vortices(0, 32, 32)
+    p2 = enomr.Problem.euler2d(32, 32, hx, hy, 5)
+    with pytest.raises(enomr.EnomrError):
+        enomr.Batch(ctx, [p2], [torch.from_numpy(U2).cuda()])
