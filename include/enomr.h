@@ -166,6 +166,34 @@ enomr_status enomr_profile_start(enomr_ctx *ctx);
 enomr_status enomr_profile_stop(enomr_ctx *ctx, double *ms, int64_t *launches);
 
 /*
+ * Frozen-stencil discrete adjoint (1D Euler problems).
+ *
+ * With the stencil choices, the per-stage alpha and the step size fixed from a
+ * forward pass, one SSP-RK3 step (Sec. 2.3, Eq. TVD3rdRK) of the operator
+ * (Sec. 2.1 Eq. 1DWENOFD with the LF split of Eq. LF_Flux_Split, the Roe-face
+ * projection and the chosen stencils of Sec. 3.2) is a smooth map of U; these
+ * calls apply the transpose of its Jacobian.
+ *
+ * enomr_ssprk3_step_record: one step of U in place with dt from the CFL rule
+ *   (bitwise the step enomr_advance takes), recording what the adjoint needs:
+ *   stages = [U^n, U^(1), U^(2)] (3 states), idx_log = the three stages' stencil
+ *   logs (layout of enomr_rhs), alpha_log[3] = each stage's alpha, *dt_dev.
+ * enomr_rhs_adjoint: lam_U = (dL/dU)^T lam_dUdt at state U with frozen idx (one
+ *   stage log) and alpha (device scalar).
+ * enomr_ssprk3_step_adjoint: lam (in: adjoint of U^{n+1}; out: adjoint of U^n)
+ *   through the recorded step.
+ * All arrays are device arrays; ws as from enomr_workspace_size().
+ */
+enomr_status enomr_rhs_adjoint(enomr_ctx *ctx, const enomr_problem *prob, const double *U, const uint8_t *idx,
+                               const double *alpha_dev, const double *lam_dUdt, double *lam_U, void *ws);
+enomr_status enomr_ssprk3_step_record(enomr_ctx *ctx, const enomr_problem *prob, double *U, double cfl,
+                                      double *stages, uint8_t *idx_log, double *alpha_log, double *dt_dev,
+                                      void *ws);
+enomr_status enomr_ssprk3_step_adjoint(enomr_ctx *ctx, const enomr_problem *prob, const double *stages,
+                                       const uint8_t *idx_log, const double *alpha_log, const double *dt_dev,
+                                       double *lam, void *ws);
+
+/*
  * Batched persistent execution: many independent 1D Euler problems (uneven
  * lengths and orders) advanced together by one persistent launch replayed
  * from a hipGraph.  Each problem advances with its own per-stage alpha and

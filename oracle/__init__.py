@@ -76,6 +76,8 @@ def lib():
         L.orc_euler2d_rhs_cells.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_long, ctypes.c_long, ctypes.c_double, ctypes.c_double,
                                             _dp, ctypes.c_long, _lp, _dp]
+        L.orc_euler1d_rhs_frozen.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_long,
+                                             ctypes.c_double, _dp, _dp, _u8p, ctypes.c_double, _dp, _dp]
         L.orc_euler_maxspeed.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long, _dp, _dp]
         L.orc_euler2d_maxspeeds.argtypes = [ctypes.c_double, ctypes.c_long, ctypes.c_long, _dp, _dp, _dp]
         L.orc_ssprk3_combine.restype = None
@@ -223,6 +225,34 @@ def euler1d_rhs(order, U, h, gamma=1.4, bc=OUTFLOW, with_idx=False):
     if with_idx:
         return out, idx.reshape(n + 1, 3, 2), alpha.value
     return out
+
+
+def euler1d_rhs_frozen(order, U, h, idx, alpha, dU=None, gamma=1.4, bc=OUTFLOW):
+    """Frozen-stencil operator L(U; idx, alpha) and, if dU is given, its
+    tangent dL/dU . dU (dual numbers).  Returns L or (L, dL)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    n = U.shape[1]
+    idx = np.ascontiguousarray(idx, dtype=np.uint8).reshape(-1)
+    out = np.empty_like(U)
+    dout = np.empty_like(U) if dU is not None else None
+    dUc = None if dU is None else np.ascontiguousarray(dU, dtype=np.float64)
+    _check(lib().orc_euler1d_rhs_frozen(table(order), gamma, bc, n, 1.0 / h, _p(U), _p(dUc), _u8(idx), alpha,
+                                        _p(out), _p(dout)), "euler1d_rhs_frozen")
+    return out if dU is None else (out, dout)
+
+
+def euler1d_rhs_frozen_jacobian(order, U, h, idx, alpha, gamma=1.4, bc=OUTFLOW):
+    """Dense Jacobian of the frozen operator, [3n][3n], column by column from tangents."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    n = U.shape[1]
+    J = np.empty((3 * n, 3 * n))
+    e = np.zeros_like(U)
+    for col in range(3 * n):
+        e.reshape(-1)[col] = 1.0
+        _, dL = euler1d_rhs_frozen(order, U, h, idx, alpha, e, gamma, bc)
+        J[:, col] = dL.reshape(-1)
+        e.reshape(-1)[col] = 0.0
+    return J
 
 
 def euler2d_rhs(order, U, hx, hy, gamma=1.4, bcx=PERIODIC, bcy=OUTFLOW, with_idx=False):

@@ -696,3 +696,154 @@ done:
     free(un); free(us); free(L);
     return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Frozen-stencil 1D Euler operator with its tangent (dual numbers)          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * With the stencil choices (idx), the line's alpha and therefore every
+ * branch fixed, L(U) is a smooth function of U.  Each quantity below carries
+ * its value (computed with exactly the operations of the forward operator
+ * above, so the value part equals L(U) when idx and alpha are the ones the
+ * forward chose) and its directional derivative along dU.
+ */
+typedef struct {
+    double v, d;
+} dual;
+
+static dual D(double v) { dual r = {v, 0.0}; return r; }
+static dual dadd(dual a, dual b) { dual r = {a.v + b.v, a.d + b.d}; return r; }
+static dual dsub(dual a, dual b) { dual r = {a.v - b.v, a.d - b.d}; return r; }
+static dual dmul(dual a, dual b) { dual r = {a.v * b.v, a.d * b.v + a.v * b.d}; return r; }
+static dual dscale(double c, dual a) { dual r = {c * a.v, c * a.d}; return r; }
+static dual dinv(dual a) { dual r = {1.0 / a.v, -a.d / (a.v * a.v)}; return r; }
+static dual dsqrt(dual a) { double s = sqrt(a.v); dual r = {s, a.d / (2.0 * s)}; return r; }
+static dual dfma(dual a, dual b, dual c) { dual r = {fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d}; return r; }
+
+/* chain acc = c[0] x[0]; acc = fma(c[i], x[i], acc) */
+static dual ddot(const dual *c, const dual *x, int n)
+{
+    dual acc = dmul(c[0], x[0]);
+    for (int i = 1; i < n; ++i) acc = dfma(c[i], x[i], acc);
+    return acc;
+}
+
+/* recon of one window with a frozen choice k (frame as in recon_face) */
+static dual recon_frozen(const orc_table *T, const dual *f, long j, int sign, int k)
+{
+    const int s = sign > 0 ? 1 : -1;
+    const long c = sign > 0 ? j : j + 1;
+#define FD(l) (f[c + (long)s * (l)])
+    const int m = T->m[k], n = T->n[k];
+    if (m >= 1 && n >= 1) {
+        int l0 = (s > 0) ? -m : n, dl = (s > 0) ? 1 : -1, l = l0;
+        dual acc = dmul(D(T->a[k][l + m]), FD(l));
+        for (int q = 1; q < m + n + 1; ++q) {
+            l += dl;
+            acc = dfma(D(T->a[k][l + m]), FD(l), acc);
+        }
+        return acc;
+    }
+    dual f0 = FD(0), mm;
+    if (m == 0 && n == 1) mm = dsub(FD(1), f0);          /* S_j^{j+1} branch */
+    else if (m == 1 && n == 0) mm = dsub(f0, FD(-1));    /* S_{j-1}^j branch */
+    else mm = D(0.0);                                     /* S_j^j */
+#undef FD
+    return dadd(f0, dscale(0.5, mm));
+}
+
+/*
+ * Frozen operator and tangent: L = L(U; idx, alpha), dL = dL/dU . dU.
+ * U, dU, L, dL: [3][n]; idx: [n+1][3][2] as from orc_euler1d_rhs.  dU and dL
+ * may be NULL (value only).
+ */
+int orc_euler1d_rhs_frozen(const orc_table *T, double gamma, int bc, long n, double ih, const double *U,
+                           const double *dU, const uint8_t *idx, double alpha, double *L, double *dL)
+{
+    if (!T || n < 2 || !idx) return ORC_EINVAL;
+    const long g = T->r + 1;
+    const long nn = n + 2 * g;
+    const double gm1 = gamma - 1.0;
+    dual *Uc = (dual *)malloc(sizeof(dual) * nn * 3);
+    dual *Gp = (dual *)malloc(sizeof(dual) * nn * 3);
+    dual *Gm = (dual *)malloc(sizeof(dual) * nn * 3);
+    dual *un = (dual *)malloc(sizeof(dual) * nn);
+    dual *H = (dual *)malloc(sizeof(dual) * nn);
+    dual *sq = (dual *)malloc(sizeof(dual) * nn);
+    dual *wp = (dual *)malloc(sizeof(dual) * nn);
+    dual *wm = (dual *)malloc(sizeof(dual) * nn);
+    dual *Fh = (dual *)malloc(sizeof(dual) * (n + 1) * 3);
+    int st = ORC_OK;
+    if (!Uc || !Gp || !Gm || !un || !H || !sq || !wp || !wm || !Fh) { st = ORC_EINVAL; goto done; }
+    for (long i = 0; i < nn; ++i) {
+        long src = map_cell(i - g, n, bc);
+        dual rho = {U[src], dU ? dU[src] : 0.0};
+        dual mn = {U[n + src], dU ? dU[n + src] : 0.0};
+        dual E = {U[2 * n + src], dU ? dU[2 * n + src] : 0.0};
+        dual ir = dinv(rho);
+        dual u = dmul(mn, ir);
+        dual ke = dscale(0.5, dmul(mn, u));
+        dual p = dscale(gm1, dsub(E, ke));
+        if (!(rho.v > 0.0) || !(p.v > 0.0)) { st = ORC_ENONPHYS; goto done; }
+        dual F[3] = {mn, dadd(dmul(mn, u), p), dmul(dadd(E, p), u)};
+        dual Ucs[3] = {rho, mn, E};
+        for (int v = 0; v < 3; ++v) {
+            dual t = dscale(alpha, Ucs[v]);
+            Uc[i * 3 + v] = Ucs[v];
+            Gp[i * 3 + v] = dscale(0.5, dadd(F[v], t));
+            Gm[i * 3 + v] = dscale(0.5, dsub(F[v], t));
+        }
+        un[i] = u;
+        H[i] = dmul(dadd(E, p), ir);
+        sq[i] = dsqrt(rho);
+    }
+    for (long f = 0; f <= n; ++f) {
+        long j = f - 1 + g;
+        /* Roe eigenvectors, the formulas of roe_eigen() in dual arithmetic */
+        dual id = dinv(dadd(sq[j], sq[j + 1]));
+        dual u = dmul(dadd(dmul(sq[j], un[j]), dmul(sq[j + 1], un[j + 1])), id);
+        dual Hr = dmul(dadd(dmul(sq[j], H[j]), dmul(sq[j + 1], H[j + 1])), id);
+        dual q2 = dmul(u, u);
+        dual c2 = dscale(gm1, dsub(Hr, dscale(0.5, q2)));
+        if (!(c2.v > 0.0)) { st = ORC_ENONPHYS; goto done; }
+        dual c = dsqrt(c2);
+        dual k = dscale(gm1, dinv(c2));
+        k.v = gm1 / c2.v;                     /* the forward divides once */
+        dual ic = dinv(c);
+        dual hq = dmul(dscale(0.5, k), q2);
+        dual ku = dmul(k, u);
+        dual uic = dmul(u, ic);
+        dual uc = dmul(u, c);
+        dual Lm[3][3] = {
+            {dscale(0.5, dadd(hq, uic)), dscale(-0.5, dadd(ku, ic)), dscale(0.5, k)},
+            {dsub(D(1.0), hq), ku, dscale(-1.0, k)},
+            {dscale(0.5, dsub(hq, uic)), dscale(-0.5, dsub(ku, ic)), dscale(0.5, k)},
+        };
+        dual Rm[3][3] = {
+            {D(1.0), D(1.0), D(1.0)},
+            {dsub(u, c), u, dadd(u, c)},
+            {dsub(Hr, uc), dscale(0.5, q2), dadd(Hr, uc)},
+        };
+        dual what[3];
+        for (int q = 0; q < 3; ++q) {
+            for (long i = j - T->r + 1; i <= j + T->r; ++i) {
+                wp[i] = ddot(Lm[q], &Gp[i * 3], 3);
+                wm[i] = ddot(Lm[q], &Gm[i * 3], 3);
+            }
+            int kp = idx[(f * 3 + q) * 2 + 0], km = idx[(f * 3 + q) * 2 + 1];
+            if (kp >= T->ncand || km >= T->ncand) { st = ORC_EINVAL; goto done; }
+            what[q] = dadd(recon_frozen(T, wp, j, +1, kp), recon_frozen(T, wm, j, -1, km));
+        }
+        for (int v = 0; v < 3; ++v) Fh[f * 3 + v] = ddot(Rm[v], what, 3);
+    }
+    for (int v = 0; v < 3; ++v)
+        for (long i = 0; i < n; ++i) {
+            dual d = dsub(Fh[(i + 1) * 3 + v], Fh[i * 3 + v]);
+            L[v * n + i] = -(d.v * ih);
+            if (dL) dL[v * n + i] = -(d.d * ih);
+        }
+done:
+    free(Uc); free(Gp); free(Gm); free(un); free(H); free(sq); free(wp); free(wm); free(Fh);
+    return st;
+}

@@ -95,6 +95,9 @@ def lib():
             "enomr_check": ([_vp], st),
             "enomr_profile_start": ([_vp], st),
             "enomr_profile_stop": ([_vp, _vp, _vp], st),
+            "enomr_rhs_adjoint": ([_vp, P, _vp, _vp, _vp, _vp, _vp, _vp], st),
+            "enomr_ssprk3_step_record": ([_vp, P, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp], st),
+            "enomr_ssprk3_step_adjoint": ([_vp, P, _vp, _vp, _vp, _vp, _vp, _vp], st),
             "enomr_batch_create": ([_vp, ctypes.c_int32, P, _vp, ctypes.c_int, ctypes.POINTER(_vp)], st),
             "enomr_batch_advance": ([_vp, ctypes.c_double, ctypes.c_int64], st),
             "enomr_batch_info": ([_vp, _vp, _vp, _vp], st),
@@ -222,6 +225,30 @@ class Context:
         self._sync_stream()
         _call("enomr_check", self.handle)
 
+    # -- frozen-stencil adjoint (1D Euler) ------------------------------------
+
+    def rhs_adjoint(self, prob, U, idx, alpha_dev, lam_dUdt):
+        """(dL/dU)^T lam_dUdt of the operator with frozen stencils idx and alpha."""
+        self._check_state(prob, U)
+        out = self.torch.empty_like(U)
+        self._sync_stream()
+        _call("enomr_rhs_adjoint", self.handle, ctypes.byref(prob), _ptr(U), _ptr(idx), _ptr(alpha_dev),
+              _ptr(lam_dUdt), _ptr(out), _ptr(self.workspace(prob)))
+        return out
+
+    def step_record(self, prob, U, cfl, stages, idx_log, alpha_log, dt_dev):
+        """One SSP-RK3 step of U in place, recording stages, stencil logs, alphas, dt."""
+        self._check_state(prob, U)
+        self._sync_stream()
+        _call("enomr_ssprk3_step_record", self.handle, ctypes.byref(prob), _ptr(U), cfl, _ptr(stages),
+              _ptr(idx_log), _ptr(alpha_log), _ptr(dt_dev), _ptr(self.workspace(prob)))
+
+    def step_adjoint(self, prob, stages, idx_log, alpha_log, dt_dev, lam):
+        """lam <- (dU^{n+1}/dU^n)^T lam through one recorded step (in place)."""
+        self._sync_stream()
+        _call("enomr_ssprk3_step_adjoint", self.handle, ctypes.byref(prob), _ptr(stages), _ptr(idx_log),
+              _ptr(alpha_log), _ptr(dt_dev), _ptr(lam), _ptr(self.workspace(prob)))
+
     def profile_start(self):
         _call("enomr_profile_start", self.handle)
 
@@ -277,4 +304,76 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _solve_forward(ctx, prob, U0, cfl, nsteps, every):
+    """Advance U0 by nsteps, keeping a copy of the state every `every` steps."""
+    U = U0.detach().clone()
+    ckpts = []
+    done = 0
+    while done < nsteps:
+        ckpts.append(U.clone())
+        k = min(every, nsteps - done)
+        ctx.advance(prob, U, cfl, k)
+        done += k
+    return U, ckpts
+
+
+def _solve_adjoint(ctx, prob, ckpts, cfl, nsteps, every, lam):
+    """Reverse through the checkpointed run: each segment is recomputed from
+    its checkpoint with recording, then its steps are transposed in reverse."""
+    t = ctx.torch
+    dev = ctx.device
+    ns = lam.numel()
+    ib = prob.idx_bytes()
+    stages = t.empty((every, 3, ns), dtype=t.float64, device=dev)
+    idx = t.empty((every, 3 * ib), dtype=t.uint8, device=dev)
+    alpha = t.empty((every, 3), dtype=t.float64, device=dev)
+    dts = t.empty((every, 1), dtype=t.float64, device=dev)
+    lam = lam.detach().clone().contiguous()
+    for seg in reversed(range(len(ckpts))):
+        k = min(every, nsteps - seg * every)
+        U = ckpts[seg].clone()
+        for s in range(k):
+            ctx.step_record(prob, U, cfl, stages[s], idx[s], alpha[s], dts[s])
+        for s in reversed(range(k)):
+            ctx.step_adjoint(prob, stages[s], idx[s], alpha[s], dts[s], lam)
+    return lam
+
+
+def _autograd_function():
+    import torch
+
+    class EnoMRSolve(torch.autograd.Function):
+        """U_T = SSP-RK3^nsteps(U_0) of a 1D Euler problem on the GPU.  The
+        backward pass is the frozen-stencil discrete adjoint (stencil choices,
+        per-stage alphas and step sizes of the forward run held fixed) with the
+        run checkpointed every `checkpoint_every` steps."""
+
+        @staticmethod
+        def forward(fctx, U0, ctx, prob, cfl, nsteps, checkpoint_every):
+            UT, ckpts = _solve_forward(ctx, prob, U0, cfl, nsteps, checkpoint_every)
+            fctx.enomr = (ctx, prob, cfl, nsteps, checkpoint_every, ckpts)
+            return UT
+
+        @staticmethod
+        def backward(fctx, grad):
+            ctx, prob, cfl, nsteps, every, ckpts = fctx.enomr
+            g = _solve_adjoint(ctx, prob, ckpts, cfl, nsteps, every, grad.contiguous())
+            return g, None, None, None, None, None
+
+    return EnoMRSolve
+
+
+_EnoMRSolve = None
+
+
+def solve(ctx, prob, U0, cfl, nsteps, checkpoint_every=20):
+    """Differentiable SSP-RK3 run (see EnoMRSolve): returns U after nsteps."""
+    global _EnoMRSolve
+    if _EnoMRSolve is None:
+        _EnoMRSolve = _autograd_function()
+    if prob.system != EULER or prob.ndim != 1:
+        raise ValueError("the differentiable solve is provided for 1D Euler problems")
+    return _EnoMRSolve.apply(U0, ctx, prob, cfl, nsteps, checkpoint_every)
 
