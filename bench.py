@@ -232,6 +232,54 @@ def run_batched(args):
             "speedup_vs_per_problem": value / value_pp, "sample_bitwise_equal": bool(same)}
 
 
+def run_adjoint(args):
+    """Adjoint workload: 1D Euler, N = 8192, order 9, smooth periodic data, 400
+    SSP-RK3 steps checkpointed every 20; loss = h sum (rho_T - rho*)^2.
+    Reports t(backward: segment recompute + reverse sweep) / t(plain forward)."""
+    import torch
+
+    import paper_2311_15504_amd as enomr
+    import workloads
+
+    n, order, nsteps, every, cfl = 8192, 9, args.adjoint_steps, 20, 0.5
+    x, h, U0 = workloads.euler1d_smooth_periodic(args.seed, n)
+    target = torch.from_numpy(workloads.density_target(args.seed, n)).cuda()
+    prob = enomr.Problem.euler1d(n, h, order, bc=enomr.PERIODIC)
+    ctx = enomr.Context(0)
+    U0d = torch.from_numpy(U0).cuda()
+    # warm-up of every path
+    U = U0d.clone().requires_grad_(True)
+    J = h * ((enomr.solve(ctx, prob, U, cfl, every, every)[0] - target) ** 2).sum()
+    J.backward()
+    ctx.check()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    # plain forward
+    V = U0d.clone()
+    torch.cuda.synchronize()
+    e[0].record()
+    ctx.advance(prob, V, cfl, nsteps)
+    e[1].record()
+    torch.cuda.synchronize()
+    t_fwd = e[0].elapsed_time(e[1])
+    # forward with checkpoints, then backward
+    UT, ckpts = enomr._solve_forward(ctx, prob, U0d, cfl, nsteps, every)
+    lamT = torch.zeros_like(UT)
+    lamT[0] = 2.0 * h * (UT[0] - target)
+    torch.cuda.synchronize()
+    e[2].record()
+    g = enomr._solve_adjoint(ctx, prob, ckpts, cfl, nsteps, every, lamT)
+    e[3].record()
+    torch.cuda.synchronize()
+    ctx.check()
+    t_bwd = e[2].elapsed_time(e[3])
+    ok = bool(torch.isfinite(g).all())
+    ctx.close()
+    return {"workload": "1D Euler N=8192 order 9, %d SSP-RK3 steps, checkpoint every %d, frozen-stencil adjoint"
+                        % (nsteps, every),
+            "forward_ms": t_fwd, "backward_ms": t_bwd, "adjoint_fwd_ratio": t_bwd / t_fwd,
+            "cell_updates_per_s_forward": n * 3 * nsteps / (t_fwd * 1e-3), "gradient_finite": ok}
+
+
 def cpu_baseline(args):
     """The oracle (single thread) on a 512 x 512 window of the same initial state, one step."""
     import oracle
@@ -264,6 +312,8 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-sample", type=int, default=64)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=400)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -272,6 +322,7 @@ def main():
         sys.exit(2)
     out = run(args)
     out["batched"] = None if args.no_batched else run_batched(args)
+    out["adjoint"] = None if args.no_adjoint else run_adjoint(args)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args)
     print(json.dumps(out), flush=True)
 

@@ -174,24 +174,26 @@ enomr_status enomr_profile_stop(enomr_ctx *ctx, double *ms, int64_t *launches);
  * projection and the chosen stencils of Sec. 3.2) is a smooth map of U; these
  * calls apply the transpose of its Jacobian.
  *
- * enomr_ssprk3_step_record: one step of U in place with dt from the CFL rule
- *   (bitwise the step enomr_advance takes), recording what the adjoint needs:
- *   stages = [U^n, U^(1), U^(2)] (3 states), idx_log = the three stages' stencil
- *   logs (layout of enomr_rhs), alpha_log[3] = each stage's alpha, *dt_dev.
+ * enomr_record_steps: nsteps SSP-RK3 steps of U in place with dt from the CFL
+ *   rule (bitwise the steps enomr_advance takes), recording per step k:
+ *   stages[k] = [U^n, U^(1), U^(2)] (3 states), idx_log[k] = the three stages'
+ *   stencil logs (layout of enomr_rhs, 3 * log size bytes), alpha_log[3k..3k+2]
+ *   = each stage's alpha, dt_log[k] = the step size.
+ * enomr_adjoint_steps: lam (in: adjoint of the state after the recorded steps;
+ *   out: adjoint of the state before them), through the recorded steps in
+ *   reverse order.
  * enomr_rhs_adjoint: lam_U = (dL/dU)^T lam_dUdt at state U with frozen idx (one
- *   stage log) and alpha (device scalar).
- * enomr_ssprk3_step_adjoint: lam (in: adjoint of U^{n+1}; out: adjoint of U^n)
- *   through the recorded step.
+ *   stage log) and alpha (device scalar); lam_U must not alias lam_dUdt
+ *   (ENOMR_EINVAL).
  * All arrays are device arrays; ws as from enomr_workspace_size().
  */
 enomr_status enomr_rhs_adjoint(enomr_ctx *ctx, const enomr_problem *prob, const double *U, const uint8_t *idx,
                                const double *alpha_dev, const double *lam_dUdt, double *lam_U, void *ws);
-enomr_status enomr_ssprk3_step_record(enomr_ctx *ctx, const enomr_problem *prob, double *U, double cfl,
-                                      double *stages, uint8_t *idx_log, double *alpha_log, double *dt_dev,
-                                      void *ws);
-enomr_status enomr_ssprk3_step_adjoint(enomr_ctx *ctx, const enomr_problem *prob, const double *stages,
-                                       const uint8_t *idx_log, const double *alpha_log, const double *dt_dev,
-                                       double *lam, void *ws);
+enomr_status enomr_record_steps(enomr_ctx *ctx, const enomr_problem *prob, double *U, double cfl, int64_t nsteps,
+                                double *stages, uint8_t *idx_log, double *alpha_log, double *dt_log, void *ws);
+enomr_status enomr_adjoint_steps(enomr_ctx *ctx, const enomr_problem *prob, int64_t nsteps, const double *stages,
+                                 const uint8_t *idx_log, const double *alpha_log, const double *dt_log, double *lam,
+                                 void *ws);
 
 /*
  * Batched persistent execution: many independent 1D Euler problems (uneven

@@ -96,8 +96,8 @@ def lib():
             "enomr_profile_start": ([_vp], st),
             "enomr_profile_stop": ([_vp, _vp, _vp], st),
             "enomr_rhs_adjoint": ([_vp, P, _vp, _vp, _vp, _vp, _vp, _vp], st),
-            "enomr_ssprk3_step_record": ([_vp, P, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp], st),
-            "enomr_ssprk3_step_adjoint": ([_vp, P, _vp, _vp, _vp, _vp, _vp, _vp], st),
+            "enomr_record_steps": ([_vp, P, _vp, ctypes.c_double, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp], st),
+            "enomr_adjoint_steps": ([_vp, P, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp], st),
             "enomr_batch_create": ([_vp, ctypes.c_int32, P, _vp, ctypes.c_int, ctypes.POINTER(_vp)], st),
             "enomr_batch_advance": ([_vp, ctypes.c_double, ctypes.c_int64], st),
             "enomr_batch_info": ([_vp, _vp, _vp, _vp], st),
@@ -236,18 +236,40 @@ class Context:
               _ptr(lam_dUdt), _ptr(out), _ptr(self.workspace(prob)))
         return out
 
-    def step_record(self, prob, U, cfl, stages, idx_log, alpha_log, dt_dev):
-        """One SSP-RK3 step of U in place, recording stages, stencil logs, alphas, dt."""
+    def _check_log(self, prob, nsteps, stages, idx_log, alpha_log, dt_log):
+        t = self.torch
+        ns = 3 * prob.nx
+        need = ((stages, t.float64, 3 * ns), (idx_log, t.uint8, 3 * prob.idx_bytes()),
+                (alpha_log, t.float64, 3), (dt_log, t.float64, 1))
+        for arr, dtype, per_step in need:
+            if arr.dtype != dtype or not arr.is_cuda or not arr.is_contiguous() or arr.numel() < nsteps * per_step:
+                raise ValueError("step log arrays must be contiguous CUDA tensors holding %d steps" % nsteps)
+
+    def record_steps(self, prob, U, cfl, nsteps, stages, idx_log, alpha_log, dt_log):
+        """nsteps SSP-RK3 steps of U in place, recording stages, stencil logs, alphas, dts."""
         self._check_state(prob, U)
+        self._check_log(prob, nsteps, stages, idx_log, alpha_log, dt_log)
         self._sync_stream()
-        _call("enomr_ssprk3_step_record", self.handle, ctypes.byref(prob), _ptr(U), cfl, _ptr(stages),
-              _ptr(idx_log), _ptr(alpha_log), _ptr(dt_dev), _ptr(self.workspace(prob)))
+        _call("enomr_record_steps", self.handle, ctypes.byref(prob), _ptr(U), cfl, nsteps, _ptr(stages),
+              _ptr(idx_log), _ptr(alpha_log), _ptr(dt_log), _ptr(self.workspace(prob)))
+
+    def adjoint_steps(self, prob, nsteps, stages, idx_log, alpha_log, dt_log, lam):
+        """lam <- adjoint through the recorded steps, last first (in place)."""
+        self._check_state(prob, lam)
+        self._check_log(prob, nsteps, stages, idx_log, alpha_log, dt_log)
+        self._sync_stream()
+        _call("enomr_adjoint_steps", self.handle, ctypes.byref(prob), nsteps, _ptr(stages), _ptr(idx_log),
+              _ptr(alpha_log), _ptr(dt_log), _ptr(lam), _ptr(self.workspace(prob)))
+
+    def step_record(self, prob, U, cfl, stages, idx_log, alpha_log, dt_dev):
+        """One recorded step (record_steps with nsteps = 1)."""
+        self.record_steps(prob, U, cfl, 1, stages, idx_log, alpha_log, dt_dev)
 
     def step_adjoint(self, prob, stages, idx_log, alpha_log, dt_dev, lam):
-        """lam <- (dU^{n+1}/dU^n)^T lam through one recorded step (in place)."""
-        self._sync_stream()
-        _call("enomr_ssprk3_step_adjoint", self.handle, ctypes.byref(prob), _ptr(stages), _ptr(idx_log),
-              _ptr(alpha_log), _ptr(dt_dev), _ptr(lam), _ptr(self.workspace(prob)))
+        """The adjoint of one recorded step (adjoint_steps with nsteps = 1)."""
+        self.adjoint_steps(prob, 1, stages, idx_log, alpha_log, dt_dev, lam)
+
+    # -- profiling ----------------------------------------------------------
 
     def profile_start(self):
         _call("enomr_profile_start", self.handle)
@@ -334,10 +356,8 @@ def _solve_adjoint(ctx, prob, ckpts, cfl, nsteps, every, lam):
     for seg in reversed(range(len(ckpts))):
         k = min(every, nsteps - seg * every)
         U = ckpts[seg].clone()
-        for s in range(k):
-            ctx.step_record(prob, U, cfl, stages[s], idx[s], alpha[s], dts[s])
-        for s in reversed(range(k)):
-            ctx.step_adjoint(prob, stages[s], idx[s], alpha[s], dts[s], lam)
+        ctx.record_steps(prob, U, cfl, k, stages, idx, alpha, dts)
+        ctx.adjoint_steps(prob, k, stages, idx, alpha, dts, lam)
     return lam
 
 

@@ -104,7 +104,7 @@ enomr_status check_problem(const enomr_problem* p)
 // Workspace: two stage states, one operator buffer, per-line alphas and a
 // few device scalars.
 struct Layout {
-    size_t U1, U2, L, ax, ay, dt, t, active, adj_face, adj_tmp, total;
+    size_t U1, U2, L, ax, ay, dt, t, active, adj_tmp, total;
 };
 
 Layout layout(const enomr_problem& p)
@@ -120,10 +120,9 @@ Layout layout(const enomr_problem& p)
     w.dt = off; off += 256;
     w.t = off; off += 256;
     w.active = off; off += 256;
-    // frozen-stencil adjoint (1D Euler): per-face buffer and four state-sized temporaries
+    // frozen-stencil adjoint (1D Euler): three state-sized temporaries
     const bool adj = p.system == ENOMR_EULER && p.ndim == 1;
-    w.adj_face = off; off += adj ? align_up(sizeof(double) * kFaceAdj * (size_t)(p.nx + 1)) : 0;
-    w.adj_tmp = off; off += adj ? 4 * align_up(state) : 0;
+    w.adj_tmp = off; off += adj ? 3 * align_up(state) : 0;
     w.total = off;
     return w;
 }
@@ -326,29 +325,88 @@ enomr_status rk3_step(enomr_ctx* ctx, const enomr_problem& p, double* U, const d
     return ENOMR_OK;
 }
 
-// lam_U = (dL/dU)^T lam_L for the frozen 1D Euler operator.
-enomr_status launch_rhs_adjoint(enomr_ctx* ctx, const enomr_problem& p, const double* U, const uint8_t* idx,
-                                const double* alpha, const double* lamL, double* lamU, void* ws)
+// One reverse stage of the frozen 1D Euler operator (see AdjIn): one launch,
+// kAdjT cells per workgroup.
+constexpr int kAdjT = 64, kAdjNT = 128;
+
+enomr_status launch_adjoint_stage(enomr_ctx* ctx, const enomr_problem& p, AdjIn a)
 {
-    const Layout w = layout(p);
-    AdjIn a;
-    a.U = U;
-    a.idx = idx;
-    a.alpha = alpha;
-    a.lamL = lamL;
-    a.face = at<double>(ws, w.adj_face);
-    a.lamU = lamU;
     a.status = ctx->status;
     a.n = p.nx;
     a.ih = 1.0 / p.hx;
     a.gamma = p.gamma;
     a.bc = p.bc_x;
-    DISPATCH_R(p.order, hipLaunchKernelGGL((k_adj_faces<R>), dim3(blocks_for(p.nx + 1, 128)), dim3(128), 0,
-                                          ctx->stream, a));
+    DISPATCH_R(p.order, hipLaunchKernelGGL((k_adj_stage<R, kAdjT, kAdjNT>), dim3(blocks_for(p.nx, kAdjT)),
+                                          dim3(kAdjNT), 0, ctx->stream, a));
     HIP_TRY(hipGetLastError());
-    DISPATCH_R(p.order, hipLaunchKernelGGL((k_adj_cells<R>), dim3(blocks_for(p.nx, 128)), dim3(128), 0,
-                                          ctx->stream, a));
-    HIP_TRY(hipGetLastError());
+    return ENOMR_OK;
+}
+
+// Forward steps recording what the reverse sweep needs (see the header).
+enomr_status record_steps(enomr_ctx* ctx, const enomr_problem& p, double* U, double cfl, int64_t nsteps,
+                          double* stages, uint8_t* idx_log, double* alpha_log, double* dt_log, void* ws)
+{
+    const Layout w = layout(p);
+    const size_t ns = (size_t)3 * p.nx;
+    const size_t ib = idx_bytes(p);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        double* S[3] = {stages + (3 * k) * ns, stages + (3 * k + 1) * ns, stages + (3 * k + 2) * ns};
+        uint8_t* ix = idx_log + (size_t)k * 3 * ib;
+        double* al = alpha_log + 3 * k;
+        double* dt = dt_log + k;
+        HIP_TRY(hipMemcpyAsync(S[0], U, sizeof(double) * ns, hipMemcpyDeviceToDevice, ctx->stream));
+        double* outs[3] = {S[1], S[2], U};
+        for (int s = 0; s < 3; ++s) {
+            if (enomr_status st = launch_alpha(ctx, p, S[s], ws, nullptr)) return st;
+            hipLaunchKernelGGL(k_copy1, dim3(1), dim3(64), 0, ctx->stream, al + s, at<double>(ws, w.ax));
+            HIP_TRY(hipGetLastError());
+            if (s == 0)
+                if (enomr_status st = launch_dt(ctx, p, cfl, ws, dt, 0.0, nullptr, 0)) return st;
+            StageOut so;
+            so.Un = S[0];
+            so.Lprev = nullptr;
+            so.out = outs[s];
+            so.dt = dt;
+            so.stage = s + 1;
+            if (enomr_status st = launch_operator(ctx, p, S[s], so, ix + s * ib, ws, nullptr)) return st;
+        }
+    }
+    return ENOMR_OK;
+}
+
+// Reverse sweep over recorded steps, last step first; lam in place.
+enomr_status adjoint_steps(enomr_ctx* ctx, const enomr_problem& p, int64_t nsteps, const double* stages,
+                           const uint8_t* idx_log, const double* alpha_log, const double* dt_log, double* lam,
+                           void* ws)
+{
+    const Layout w = layout(p);
+    const size_t ns = (size_t)3 * p.nx;
+    const size_t ib = idx_bytes(p);
+    const size_t sb = align_up(sizeof(double) * ns);
+    double* T1 = at<double>(ws, w.adj_tmp);        // adjoint of U^(2)
+    double* T2 = at<double>(ws, w.adj_tmp + sb);   // adjoint of U^(1)
+    double* T4 = at<double>(ws, w.adj_tmp + 2 * sb);   // adjoint of U^n (partial)
+    const double c13 = 1.0 / 3.0, c23 = 2.0 / 3.0;
+    for (int64_t k = nsteps - 1; k >= 0; --k) {
+        const double* S[3] = {stages + (3 * k) * ns, stages + (3 * k + 1) * ns, stages + (3 * k + 2) * ns};
+        const uint8_t* ix = idx_log + (size_t)k * 3 * ib;
+        const double* al = alpha_log + 3 * k;
+        const double* dt = dt_log + k;
+        AdjIn a{};
+        a.dt = dt;
+        // stage 3: U^{n+1} = 1/3 U^n + 2/3 (U^(2) + dt L(U^(2)))
+        a.U = S[2]; a.idx = ix + 2 * ib; a.alpha = al + 2; a.lamIn = lam;
+        a.a = c13; a.b = c23; a.cb = c23; a.addv = nullptr; a.lamAcc = T4; a.accumulate = 0; a.lamOut = T1;
+        if (enomr_status st = launch_adjoint_stage(ctx, p, a)) return st;
+        // stage 2: U^(2) = 3/4 U^n + 1/4 (U^(1) + dt L(U^(1)))
+        a.U = S[1]; a.idx = ix + ib; a.alpha = al + 1; a.lamIn = T1;
+        a.a = 0.75; a.b = 0.25; a.cb = 0.25; a.addv = nullptr; a.lamAcc = T4; a.accumulate = 1; a.lamOut = T2;
+        if (enomr_status st = launch_adjoint_stage(ctx, p, a)) return st;
+        // stage 1: U^(1) = U^n + dt L(U^n)
+        a.U = S[0]; a.idx = ix; a.alpha = al; a.lamIn = T2;
+        a.a = 0.0; a.b = 1.0; a.cb = 1.0; a.addv = T4; a.lamAcc = nullptr; a.accumulate = 0; a.lamOut = lam;
+        if (enomr_status st = launch_adjoint_stage(ctx, p, a)) return st;
+    }
     return ENOMR_OK;
 }
 
@@ -612,77 +670,39 @@ enomr_status enomr_rhs_adjoint(enomr_ctx* ctx, const enomr_problem* prob, const 
     if (enomr_status st = check_ctx(ctx)) return st;
     if (enomr_status st = check_adjoint_problem(prob)) return st;
     if (!U || !idx || !alpha_dev || !lam_dUdt || !lam_U || !ws) return fail(ENOMR_EINVAL, "NULL array");
-    return launch_rhs_adjoint(ctx, *prob, U, idx, alpha_dev, lam_dUdt, lam_U, ws);
+    if (lam_U == lam_dUdt) return fail(ENOMR_EINVAL, "lam_U must not alias lam_dUdt");
+    AdjIn a{};
+    a.U = U;
+    a.idx = idx;
+    a.alpha = alpha_dev;
+    a.lamIn = lam_dUdt;
+    a.dt = nullptr;
+    a.a = 0.0;
+    a.b = 1.0;
+    a.cb = 0.0;
+    a.lamOut = lam_U;
+    return launch_adjoint_stage(ctx, *prob, a);
 }
 
-enomr_status enomr_ssprk3_step_record(enomr_ctx* ctx, const enomr_problem* prob, double* U, double cfl,
-                                      double* stages, uint8_t* idx_log, double* alpha_log, double* dt_dev, void* ws)
+enomr_status enomr_record_steps(enomr_ctx* ctx, const enomr_problem* prob, double* U, double cfl, int64_t nsteps,
+                                double* stages, uint8_t* idx_log, double* alpha_log, double* dt_log, void* ws)
 {
     if (enomr_status st = check_ctx(ctx)) return st;
     if (enomr_status st = check_adjoint_problem(prob)) return st;
-    if (!U || !stages || !idx_log || !alpha_log || !dt_dev || !ws) return fail(ENOMR_EINVAL, "NULL array");
-    if (!(cfl > 0.0)) return fail(ENOMR_EINVAL, "cfl must be > 0");
-    const enomr_problem& p = *prob;
-    const Layout w = layout(p);
-    const size_t ns = (size_t)3 * p.nx;
-    const size_t ib = idx_bytes(p);
-    double* S[3] = {stages, stages + ns, stages + 2 * ns};
-    HIP_TRY(hipMemcpyAsync(S[0], U, sizeof(double) * ns, hipMemcpyDeviceToDevice, ctx->stream));
-    double* outs[3] = {S[1], S[2], U};
-    for (int s = 0; s < 3; ++s) {
-        if (enomr_status st = launch_alpha(ctx, p, S[s], ws, nullptr)) return st;
-        hipLaunchKernelGGL(k_copy1, dim3(1), dim3(64), 0, ctx->stream, alpha_log + s, at<double>(ws, w.ax));
-        HIP_TRY(hipGetLastError());
-        if (s == 0)
-            if (enomr_status st = launch_dt(ctx, p, cfl, ws, dt_dev, 0.0, nullptr, 0)) return st;
-        StageOut so;
-        so.Un = S[0];
-        so.Lprev = nullptr;
-        so.out = outs[s];
-        so.dt = dt_dev;
-        so.stage = s + 1;
-        if (enomr_status st = launch_operator(ctx, p, S[s], so, idx_log + s * ib, ws, nullptr)) return st;
-    }
-    return ENOMR_OK;
+    if (!U || !stages || !idx_log || !alpha_log || !dt_log || !ws) return fail(ENOMR_EINVAL, "NULL array");
+    if (!(cfl > 0.0) || nsteps < 0) return fail(ENOMR_EINVAL, "bad cfl or nsteps");
+    return record_steps(ctx, *prob, U, cfl, nsteps, stages, idx_log, alpha_log, dt_log, ws);
 }
 
-enomr_status enomr_ssprk3_step_adjoint(enomr_ctx* ctx, const enomr_problem* prob, const double* stages,
-                                       const uint8_t* idx_log, const double* alpha_log, const double* dt_dev,
-                                       double* lam, void* ws)
+enomr_status enomr_adjoint_steps(enomr_ctx* ctx, const enomr_problem* prob, int64_t nsteps, const double* stages,
+                                 const uint8_t* idx_log, const double* alpha_log, const double* dt_log, double* lam,
+                                 void* ws)
 {
     if (enomr_status st = check_ctx(ctx)) return st;
     if (enomr_status st = check_adjoint_problem(prob)) return st;
-    if (!stages || !idx_log || !alpha_log || !dt_dev || !lam || !ws) return fail(ENOMR_EINVAL, "NULL array");
-    const enomr_problem& p = *prob;
-    const Layout w = layout(p);
-    const long ns = 3 * p.nx;
-    const size_t ib = idx_bytes(p);
-    const size_t sb = align_up(sizeof(double) * ns);
-    double* T1 = at<double>(ws, w.adj_tmp);
-    double* T2 = at<double>(ws, w.adj_tmp + sb);
-    double* T3 = at<double>(ws, w.adj_tmp + 2 * sb);
-    double* T4 = at<double>(ws, w.adj_tmp + 3 * sb);
-    const double* S[3] = {stages, stages + ns, stages + 2 * ns};
-    const double c13 = 1.0 / 3.0, c23 = 2.0 / 3.0;
-    const unsigned nb = blocks_for(ns, 256);
-    hipStream_t st = ctx->stream;
-    // stage 3: U^{n+1} = 1/3 U^n + 2/3 (U2 + dt L(U2))
-    hipLaunchKernelGGL(k_axpdty, dim3(nb), dim3(256), 0, st, T2, 0.0, lam, c23, dt_dev, lam, ns);
-    if (enomr_status e = launch_rhs_adjoint(ctx, p, S[2], idx_log + 2 * ib, alpha_log + 2, T2, T3, ws)) return e;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, st, T1, c23, lam, 1.0, T3, ns);       // lambda_U2
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, st, T4, c13, lam, 0.0, nullptr, ns);  // lambda_Un
-    // stage 2: U2 = 3/4 U^n + 1/4 (U1 + dt L(U1))
-    hipLaunchKernelGGL(k_axpdty, dim3(nb), dim3(256), 0, st, T2, 0.0, T1, 0.25, dt_dev, T1, ns);
-    if (enomr_status e = launch_rhs_adjoint(ctx, p, S[1], idx_log + ib, alpha_log + 1, T2, T3, ws)) return e;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, st, T2, 0.25, T1, 1.0, T3, ns);      // lambda_U1
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, st, T4, 1.0, T4, 0.75, T1, ns);
-    // stage 1: U1 = U^n + dt L(U^n)
-    hipLaunchKernelGGL(k_axpdty, dim3(nb), dim3(256), 0, st, T1, 0.0, T2, 1.0, dt_dev, T2, ns);
-    if (enomr_status e = launch_rhs_adjoint(ctx, p, S[0], idx_log, alpha_log, T1, T3, ws)) return e;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, st, lam, 1.0, T4, 1.0, T2, ns);
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, st, lam, 1.0, lam, 1.0, T3, ns);
-    HIP_TRY(hipGetLastError());
-    return ENOMR_OK;
+    if (!stages || !idx_log || !alpha_log || !dt_log || !lam || !ws) return fail(ENOMR_EINVAL, "NULL array");
+    if (nsteps < 0) return fail(ENOMR_EINVAL, "bad nsteps");
+    return adjoint_steps(ctx, *prob, nsteps, stages, idx_log, alpha_log, dt_log, lam, ws);
 }
 
 // ---------------------------------------------------------------------------

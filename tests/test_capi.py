@@ -28,6 +28,17 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_binding_types_every_declared_symbol():
+    # The Python binding gives each entry point an argument list, so a call
+    # through it never falls back to ctypes' untyped default conversion.
+    L = enomr.lib()
+    for name in _declared_symbols():
+        assert getattr(L, name).argtypes is not None, name
+    for meth in ("recon_faces", "rhs", "dt", "ssprk3_step", "advance", "check", "profile_start",
+                 "profile_stop", "rhs_adjoint", "record_steps", "adjoint_steps"):
+        assert callable(getattr(enomr.Context, meth, None)), meth
+
+
 def test_library_coefficients_equal_oracle_doubles_bitwise():
     # The library derives a_l from Lagrange derivatives of the primitive and
     # b_l from binomials; the oracle solves the moment system exactly.  Both

@@ -28,12 +28,15 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-@pytest.mark.parametrize("order", [5, 9, 17])
+@pytest.mark.parametrize("order,n", [(5, 70), (9, 70), (17, 70), (9, 200), (17, 19), (5, 7)])
 @pytest.mark.parametrize("bc", [oracle.OUTFLOW, oracle.PERIODIC])
-def test_rhs_adjoint_is_the_transposed_jacobian(ctx, order, bc):
+def test_rhs_adjoint_is_the_transposed_jacobian(ctx, order, n, bc):
+    # n = 70: two workgroups, the second ragged; n = 200: interior workgroups
+    # whose faces come only from their neighbours' cells; n = 2r + 1 (the
+    # smallest grid accepted): the widest stencils of every face wrap
+    # (periodic) or reach ghost images at both ends (outflow).
     import torch
     import paper_2311_15504_amd as enomr
-    n = 70
     _, h, U = workloads.euler1d_riemann_perturbed(10 + order + bc, n)
     L, idx, alpha = oracle.euler1d_rhs(order, U, h, bc=bc, with_idx=True)
     J = oracle.euler1d_rhs_frozen_jacobian(order, U, h, idx, alpha, bc=bc)
@@ -44,6 +47,10 @@ def test_rhs_adjoint_is_the_transposed_jacobian(ctx, order, bc):
     got = ctx.rhs_adjoint(prob, _dev(U), torch.from_numpy(idx.reshape(-1).copy()).cuda(),
                           torch.tensor([alpha], dtype=torch.float64, device="cuda"), _dev(lam))
     ctx.check()
+    got2 = ctx.rhs_adjoint(prob, _dev(U), torch.from_numpy(idx.reshape(-1).copy()).cuda(),
+                           torch.tensor([alpha], dtype=torch.float64, device="cuda"), _dev(lam))
+    ctx.check()
+    assert torch.equal(got, got2)   # no atomics: bitwise reproducible
     got = got.cpu().numpy()
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), np.abs(got - ref).max() / np.abs(ref).max()
 
