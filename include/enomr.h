@@ -205,10 +205,10 @@ enomr_status enomr_adjoint_steps(enomr_ctx *ctx, const enomr_problem *prob, int6
  * enomr_batch_create: probs[nprob] (ndim 1, ENOMR_EULER, any order 5..17),
  * U[nprob] device pointers to the problems' [3][nx] states, bound to the batch
  * for its lifetime and advanced in place.  The batch allocates its own stage
- * workspace (2 states per problem).  autotune != 0 times one step of the
+ * workspace (2 states per problem).  autotune = 1 times one step of the
  * whole batch on scratch copies for each tile width (64, 128, 256 faces) and
- * keeps the fastest; otherwise 128.  The work queue hands out problems
- * longest first.
+ * keeps the fastest; 0 uses 128; 64, 128 or 256 use that width; any other
+ * value is ENOMR_EINVAL.  The work queue hands out problems longest first.
  * enomr_batch_advance: nsteps SSP-RK3 steps of every problem at CFL `cfl`.
  * enomr_batch_info: chosen tile width, workgroups, and the autotune times (ms,
  * for widths 64/128/256; zeros without autotune).  Any pointer may be NULL.

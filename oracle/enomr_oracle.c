@@ -12,8 +12,11 @@
  * formula is part of the specification (the paper leaves it open); the GPU
  * kernels follow the same order so that stencil choices agree bit for bit.
  *
- *   - dot products (IS, fluxes, projections): first term a plain product, then
- *     fma() terms, in ascending physical cell (or component) order;
+ *   - dot products (fluxes, projections, the full stencil's IS): first term a
+ *     plain product, then fma() terms, in ascending physical cell (or
+ *     component) order;
+ *   - IS of every other candidate: the (m+n)-th undivided difference of its
+ *     cells in ascending order, by repeated differencing f_{i+1} - f_i;
  *   - IS0 second differences: (f_c - 2 f_{c-1}) + f_{c-2};
  *   - one reciprocal per cell (1/rho) and per face (1/(sqrt(rho_L)+sqrt(rho_R)))
  *     multiplies instead of repeated divisions.
@@ -105,6 +108,21 @@ static double stencil_dot(const double *coef, int m, int n, const double *f, lon
 }
 
 /*
+ * The d-th undivided difference of f at cells first .. first+d (ascending):
+ * d rounds of replacing neighbours by f_{i+1} - f_i.  Eq. (CurrentIS) defines
+ * IS as h^{m+n} times the (m+n)-th derivative of the stencil's polynomial,
+ * which is this difference; the b_l of Table ISCoe are its binomial expansion.
+ */
+static double undivided_difference(const double *f, long first, int d)
+{
+    double t[ORC_MAXW];
+    for (int i = 0; i <= d; ++i) t[i] = f[first + i];
+    for (int lev = 1; lev <= d; ++lev)
+        for (int i = 0; i + lev <= d; ++i) t[i] = t[i + 1] - t[i];
+    return t[0];
+}
+
+/*
  * Reconstruct f-hat at face j+1/2 from cell values f (indexable from
  * j-r+1 to j+r).  sign = +1: f^+ (upwind on the left); sign = -1: f^-.
  * Writes the chosen candidate's position in the candidate list to *idx.
@@ -120,13 +138,17 @@ static double recon_face(const orc_table *T, const double *f, long j, int sign, 
     double isr = fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2));
     double is0 = fmin(isl, isr);
 
-    /* Step 2: IS = |sum b_l f_{j+l}| of every candidate, Eqs. (CurrentIS), (ISCoe).
+    /* Step 2: IS of every candidate, Eqs. (CurrentIS), (ISCoe): for the full
+       stencil |sum b_l f_{j+l}|, for the others the undivided difference over
+       the stencil's cells (leftmost physical cell c-m for f^+, c-n for f^-).
        (The paper only needs them up to the first accepted one; computing all of
        them and then scanning gives the same choice.) */
     double is[ORC_MAXC];
     for (int k = 0; k < T->ncand; ++k) {
-        if (T->m[k] >= 1 && T->n[k] >= 1)
-            is[k] = fabs(stencil_dot(T->b[k], T->m[k], T->n[k], f, c, s));
+        const int m = T->m[k], n = T->n[k];
+        if (m >= 1 && n >= 1)
+            is[k] = k == 0 ? fabs(stencil_dot(T->b[k], m, n, f, c, s))
+                           : fabs(undivided_difference(f, s > 0 ? c - m : c - n, m + n));
         else
             is[k] = 0.0;
     }

@@ -288,7 +288,9 @@ class Batch:
     (enomr_batch_*).  `states` are the problems' [3][n] float64 CUDA tensors;
     they stay bound to the batch and are advanced in place."""
 
-    def __init__(self, ctx, problems, states, autotune=True):
+    def __init__(self, ctx, problems, states, autotune=True, tile_faces=None):
+        """autotune: time the tile widths 64/128/256 and keep the fastest;
+        tile_faces: use that width instead (autotune is then ignored)."""
         if len(problems) != len(states) or not problems:
             raise ValueError("one state per problem")
         for p, U in zip(problems, states):
@@ -300,8 +302,8 @@ class Batch:
         ptrs = (ctypes.c_void_p * n)(*[U.data_ptr() for U in states])
         h = _vp()
         ctx._sync_stream()
-        _call("enomr_batch_create", ctx.handle, n, arr, ctypes.cast(ptrs, _vp), 1 if autotune else 0,
-              ctypes.byref(h))
+        mode = int(tile_faces) if tile_faces is not None else (1 if autotune else 0)
+        _call("enomr_batch_create", ctx.handle, n, arr, ctypes.cast(ptrs, _vp), mode, ctypes.byref(h))
         self.handle = h
 
     def advance(self, cfl, nsteps):

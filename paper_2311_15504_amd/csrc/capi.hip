@@ -17,7 +17,6 @@ namespace enomr {
 __constant__ double c_a[kPool][kMaxW];
 __constant__ double c_b[kPool][kMaxW];
 __constant__ double c_wa[2][kPool][kMaxW];
-__constant__ double c_wb[2][kPool][kMaxW];
 __constant__ int c_candpool[10][kPool];
 }  // namespace enomr
 
@@ -235,7 +234,7 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
         in.bc = p.bc_x;
         timed(ctx, PROF_SWEEP_X, [&] {
             DISPATCH_R(p.order,
-                       hipLaunchKernelGGL((k_euler_sweep<3, R, 0, kTF1, 1>), dim3(blocks_for(p.nx, kTF1 - 1), 1),
+                       hipLaunchKernelGGL((k_euler_sweep<3, R, 0, kTF1, 1>), dim3(blocks_for(p.nx, kTF1 - 1)),
                                           dim3(kTF1), 0, ctx->stream, in, so));
         });
         HIP_TRY(hipGetLastError());
@@ -257,7 +256,7 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
     timed(ctx, PROF_SWEEP_X, [&] {
         DISPATCH_R(p.order,
                    hipLaunchKernelGGL((k_euler_sweep<4, R, 0, kTFx, kTLx>),
-                                      dim3(blocks_for(p.nx, kTFx - 1), blocks_for(p.ny, kTLx)), dim3(kTFx * kTLx),
+                                      dim3(blocks_for(p.nx, kTFx - 1) * blocks_for(p.ny, kTLx)), dim3(kTFx * kTLx),
                                       0, ctx->stream, in, sx));
     });
     HIP_TRY(hipGetLastError());
@@ -269,7 +268,7 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
     timed(ctx, PROF_SWEEP_Y, [&] {
         DISPATCH_R(p.order,
                    hipLaunchKernelGGL((k_euler_sweep<4, R, 1, kTFy, kTLy>),
-                                      dim3(blocks_for(p.ny, kTFy - 1), blocks_for(p.nx, kTLy)), dim3(kTFy * kTLy),
+                                      dim3(blocks_for(p.ny, kTFy - 1) * blocks_for(p.nx, kTLy)), dim3(kTFy * kTLy),
                                       0, ctx->stream, in, so));
     });
     HIP_TRY(hipGetLastError());
@@ -471,18 +470,16 @@ enomr_status enomr_create(int device, void* hip_stream, enomr_ctx** out)
     static bool ready = generate_tables(ta, tb);
     (void)ready;
     // window-aligned rows (centre at entry 8) and candidate -> pool maps
-    static double wa[2][kPool][kMaxW], wb[2][kPool][kMaxW];
+    static double wa[2][kPool][kMaxW];
     static int cp[10][kPool];
     for (int P = 0; P < kPool; ++P) {
         const int m = pool_mn(P, 0), n = pool_mn(P, 1);
         for (int i = 0; i < kMaxW; ++i) {
-            wa[0][P][i] = wb[0][P][i] = wa[1][P][i] = wb[1][P][i] = 0.0;
+            wa[0][P][i] = wa[1][P][i] = 0.0;
         }
         for (int l = -m; l <= n; ++l) {
             wa[0][P][8 + l] = ta[P][l + m];   // f^+: offset l is window entry 8 + l
-            wb[0][P][8 + l] = tb[P][l + m];
             wa[1][P][8 - l] = ta[P][l + m];   // f^-: offset l is window entry 8 - l
-            wb[1][P][8 - l] = tb[P][l + m];
         }
     }
     for (int R = 0; R < 10; ++R)
@@ -490,7 +487,6 @@ enomr_status enomr_create(int device, void* hip_stream, enomr_ctx** out)
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_a), ta, sizeof(ta)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_b), tb, sizeof(tb)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_wa), wa, sizeof(wa)));
-    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_wb), wb, sizeof(wb)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_candpool), cp, sizeof(cp)));
     enomr_ctx* c = new enomr_ctx;
     c->device = device;
@@ -768,6 +764,8 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
 {
     if (enomr_status st = check_ctx(ctx)) return st;
     if (!out || !probs || !U || nprob < 1) return fail(ENOMR_EINVAL, "bad batch arguments");
+    if (autotune != 0 && autotune != 1 && autotune != 64 && autotune != 128 && autotune != 256)
+        return fail(ENOMR_EINVAL, "autotune must be 0, 1, 64, 128 or 256");
     *out = nullptr;
     std::vector<BatchProb> hp(nprob);
     std::vector<double> cost(nprob);
@@ -819,7 +817,8 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
     // Autotune the tile width: one step of the whole batch on scratch copies of
     // the states, per width; the fastest wins.
     b->tf = 128;
-    if (autotune) {
+    if (autotune == 64 || autotune == 128 || autotune == 256) b->tf = autotune;
+    if (autotune == 1) {
         size_t state_bytes = 0;
         for (int i = 0; i < nprob; ++i) state_bytes += align_up(sizeof(double) * 3 * (size_t)probs[i].nx);
         double* scratch = nullptr;

@@ -20,13 +20,12 @@ namespace enomr {
 extern __constant__ double c_a[kPool][kMaxW];
 extern __constant__ double c_b[kPool][kMaxW];
 
-// The same coefficients aligned to a 17-entry window centred at entry 8 and
-// zero outside the stencil: c_wa[s][P][i] multiplies window entry i for sign
-// s (0: +, 1: -).  A (2R-1)-entry window starts at entry 9-R.  A zero
-// coefficient adds an exact zero to an fma chain, so a padded chain rounds
-// like the stencil's own chain (up to the sign of a zero result).
+// The a_l aligned to a 17-entry window centred at entry 8 and zero outside
+// the stencil: c_wa[s][P][i] multiplies window entry i for sign s (0: +,
+// 1: -).  A (2R-1)-entry window starts at entry 9-R.  A zero coefficient adds
+// an exact zero to an fma chain, so a padded chain rounds like the stencil's
+// own chain (up to the sign of a zero result).
 extern __constant__ double c_wa[2][kPool][kMaxW];
-extern __constant__ double c_wb[2][kPool][kMaxW];
 // Pool index of candidate c of the (2R-1)-point scheme: c_candpool[R][c].
 extern __constant__ int c_candpool[10][kPool];
 
@@ -64,14 +63,12 @@ __device__ __forceinline__ double baseline_is(const double (&w)[2 * R - 1])
     return fmin(isl, isr);
 }
 
-// Step 3.2: f_c + minmod(f_{c+1} - f_c, f_c - f_{c-1}) / 2 in the sign's frame.
-template <int R, int S>
-__device__ __forceinline__ double minmod_flux(const double (&w)[2 * R - 1], int& idx)
+// Step 3.2: f_c + minmod(f_{c+1} - f_c, f_c - f_{c-1}) / 2 in the sign's frame,
+// from the centre value f0, its downwind neighbour fp1 and upwind fm1.
+template <int R>
+__device__ __forceinline__ double minmod3(double f0, double fp1, double fm1, int& idx)
 {
     constexpr int NC = n_cands(R);
-    const double f0 = w[R - 1];
-    const double fp1 = S > 0 ? w[R] : w[R - 2];
-    const double fm1 = S > 0 ? w[R - 2] : w[R];
     const double da = fp1 - f0;
     const double db = f0 - fm1;
     double mm;
@@ -84,51 +81,79 @@ __device__ __forceinline__ double minmod_flux(const double (&w)[2 * R - 1], int&
     return f0 + 0.5 * mm;
 }
 
-// Steps 3.1/3.2 from candidate C on: the first candidate (list order) with
-// m, n >= 1 and IS < IS0 gives the flux, otherwise minmod.
-template <int R, int S, int C>
-__device__ __forceinline__ double select_from(const double (&w)[2 * R - 1], double is0, int& idx)
+template <int R, int S>
+__device__ __forceinline__ double minmod_flux(const double (&w)[2 * R - 1], int& idx)
+{
+    return minmod3<R>(w[R - 1], S > 0 ? w[R] : w[R - 2], S > 0 ? w[R - 2] : w[R], idx);
+}
+
+// Step 3.1 beyond the full stencil.  The indicator of candidate (m, n) is the
+// (m+n)-th undivided difference of its cells (Eq. CurrentIS: h^{m+n} times the
+// (m+n)-th derivative of the stencil polynomial; Table ISCoe holds its binomial
+// expansion), taken by repeated differencing of the window in ascending cell
+// order.  One difference table of the window, built level by level in place,
+// yields every candidate's indicator; each candidate's pass bit is recorded at
+// its level and the lowest set bit is the first passing candidate in list
+// order.  In the sign's frame stencil (m, n) starts at window entry R-1-m
+// (f^+) or R-1-n (f^-, the mirror image).
+template <int R, int S, int LEV, int C>
+__device__ __forceinline__ void mark_level(const double (&d)[2 * R - 1], double is0, unsigned& pass)
 {
     if constexpr (C < n_cands(R)) {
         constexpr int P = cand_pool(R, C);
         constexpr int m = pool_mn(P, 0), n = pool_mn(P, 1);
-        if constexpr (m >= 1 && n >= 1) {
-            const double is = fabs(sdot<R, S, P>(c_b[P], w));
-            if (is < is0) {
-                idx = C;
-                return sdot<R, S, P>(c_a[P], w);
-            }
+        if constexpr (m >= 1 && n >= 1 && m + n == LEV) {
+            constexpr int s = S > 0 ? R - 1 - m : R - 1 - n;
+            if (fabs(d[s]) < is0) pass |= 1u << C;
         }
-        return select_from<R, S, C + 1>(w, is0, idx);
-    } else {
-        return minmod_flux<R, S>(w, idx);
+        mark_level<R, S, LEV, C + 1>(d, is0, pass);
     }
 }
 
-// Steps 3.1/3.2 from candidate 1 on with a runtime loop over the padded
-// window-aligned rows (compact code for the rarely taken non-smooth path).
-template <int R, int S>
-__device__ __forceinline__ double select_tail_loop(const double (&w)[2 * R - 1], double is0, int& idx)
+template <int R, int S, int LEV>
+__device__ __forceinline__ void difference_levels(double (&d)[2 * R - 1], double is0, unsigned& pass)
 {
-    constexpr int NC = n_cands(R);
-    constexpr int W = 2 * R - 1;
-    constexpr int off = 9 - R;
-    constexpr int s = S > 0 ? 0 : 1;
-#pragma unroll 1
-    for (int c = 1; c <= NC - 4; ++c) {
-        const int P = c_candpool[R][c];
-        const double* wb = &c_wb[s][P][off];
-        double acc = wb[0] * w[0];
+    // the full stencil's level 2R-2 is not needed: candidate 0 is tested by its b_l chain
+    if constexpr (LEV <= 2 * R - 3) {
 #pragma unroll
-        for (int i = 1; i < W; ++i) acc = fma(wb[i], w[i], acc);
-        if (fabs(acc) < is0) {
-            const double* wa = &c_wa[s][P][off];
-            double f = wa[0] * w[0];
+        for (int i = 0; i + LEV < 2 * R - 1; ++i) d[i] = d[i + 1] - d[i];
+        mark_level<R, S, LEV, 1>(d, is0, pass);
+        difference_levels<R, S, LEV + 1>(d, is0, pass);
+    }
+}
+
+// Step 3.1 from candidate 1 on: the first candidate whose indicator is below
+// is0, or -1.  The window d is overwritten by its difference table.
+template <int R, int S>
+__device__ __forceinline__ int first_passing(double (&d)[2 * R - 1], double is0)
+{
+    unsigned pass = 0;
+    difference_levels<R, S, 1>(d, is0, pass);
+    return pass ? __builtin_ctz(pass) : -1;
+}
+
+// The flux of candidate c over the window: padded window-aligned a_l row.
+template <int R, int S>
+__device__ __forceinline__ double candidate_flux(const double (&w)[2 * R - 1], int c)
+{
+    const double* wa = &c_wa[S > 0 ? 0 : 1][c_candpool[R][c]][9 - R];
+    double f = wa[0] * w[0];
 #pragma unroll
-            for (int i = 1; i < W; ++i) f = fma(wa[i], w[i], f);
-            idx = c;
-            return f;
-        }
+    for (int i = 1; i < 2 * R - 1; ++i) f = fma(wa[i], w[i], f);
+    return f;
+}
+
+// Steps 3.1/3.2 from candidate 1 on, for a window whose full stencil failed.
+template <int R, int S>
+__device__ __forceinline__ double select_rest(const double (&w)[2 * R - 1], double is0, int& idx)
+{
+    double d[2 * R - 1];
+#pragma unroll
+    for (int i = 0; i < 2 * R - 1; ++i) d[i] = w[i];
+    const int c = first_passing<R, S>(d, is0);
+    if (c >= 0) {
+        idx = c;
+        return candidate_flux<R, S>(w, c);
     }
     return minmod_flux<R, S>(w, idx);
 }
@@ -137,8 +162,13 @@ __device__ __forceinline__ double select_tail_loop(const double (&w)[2 * R - 1],
 template <int R, int S>
 __device__ __forceinline__ double recon(const double (&w)[2 * R - 1], int& idx)
 {
+    constexpr int P0 = cand_pool(R, 0);
     const double is0 = baseline_is<R, S>(w);
-    return select_from<R, S, 0>(w, is0, idx);
+    if (fabs(sdot<R, S, P0>(c_b[P0], w)) < is0) {
+        idx = 0;
+        return sdot<R, S, P0>(c_a[P0], w);
+    }
+    return select_rest<R, S>(w, is0, idx);
 }
 
 }  // namespace enomr

@@ -417,6 +417,8 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     // normal-frame component q -> global variable
     auto gvar = [](int q) { return (DIR == 1 && NV == 4) ? (q == 1 ? 2 : (q == 2 ? 1 : q)) : q; };
     auto lpos = [](int line, int cell) { return DIR == 0 ? line * NCL + cell : cell * TL + line; };
+    // face fluxes: lanes of a wave are consecutive in both directions' layouts
+    auto fpos = [](int line, int f) { return DIR == 0 ? line * TF + f : f * TL + line; };
     auto gidx = [nx](long line, long cell) { return DIR == 0 ? line * nx + cell : cell * nx + line; };
 
     // ---- stage the tile: primitives, LF split G = (F +- alpha U)/2, Roe inputs
@@ -592,29 +594,39 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
                 const int q = kk >> 1;
                 double r[NV];
                 l_row<NV>(e, q, r);
-                double w[W];
-                int id;
-                double res;
-                if ((kk & 1) == 0) {
-#pragma unroll
-                    for (int i = 0; i < W; ++i) {
-                        const int lp = lpos(tl, jp - (R - 1) + i);
-                        double G[NV];
+                // project the window (ascending cells), keep what minmod needs,
+                // then turn the window into its difference table
+                const int base = (kk & 1) == 0 ? jp - (R - 1) : jp - (R - 2);
+                auto proj = [&](int i) {
+                    const int lp = lpos(tl, base + i);
+                    double G[NV];
+                    if ((kk & 1) == 0) {
 #pragma unroll
                         for (int c = 0; c < NV; ++c) G[c] = sm.Gp[c][lp];
-                        w[i] = row_chain<NV>(r, G);
-                    }
-                    res = select_tail_loop<R, +1>(w, baseline_is<R, +1>(w), id);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < W; ++i) {
-                        const int lp = lpos(tl, jp - (R - 2) + i);
-                        double G[NV];
+                    } else {
 #pragma unroll
                         for (int c = 0; c < NV; ++c) G[c] = sm.Gm[c][lp];
-                        w[i] = row_chain<NV>(r, G);
                     }
-                    res = select_tail_loop<R, -1>(w, baseline_is<R, -1>(w), id);
+                    return row_chain<NV>(r, G);
+                };
+                double w[W];
+#pragma unroll
+                for (int i = 0; i < W; ++i) w[i] = proj(i);
+                int id;
+                double res;
+                const double f0 = w[R - 1], lo = w[R - 2], hi = w[R];
+                int c;
+                if ((kk & 1) == 0) c = first_passing<R, +1>(w, baseline_is<R, +1>(w));
+                else c = first_passing<R, -1>(w, baseline_is<R, -1>(w));
+                if (c >= 0) {
+                    // re-project (bitwise the same values) into the chosen row
+                    const double* wa = &c_wa[kk & 1][c_candpool[R][c]][9 - R];
+                    res = wa[0] * proj(0);
+#pragma unroll 1
+                    for (int i = 1; i < W; ++i) res = fma(wa[i], proj(i), res);
+                    id = c;
+                } else {
+                    res = (kk & 1) == 0 ? minmod3<R>(f0, hi, lo, id) : minmod3<R>(f0, lo, hi, id);
                 }
 #pragma unroll
                 for (int t = 0; t < NV; ++t) {
@@ -632,7 +644,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         for (int q = 0; q < NV; ++q) wh[q] = hp[q] + hm[q];
         back_project<NV>(e, wh, Fh);
 #pragma unroll
-        for (int q = 0; q < NV; ++q) sm.F[q][tl * TF + tf] = Fh[q];
+        for (int q = 0; q < NV; ++q) sm.F[q][fpos(tl, tf)] = Fh[q];
 
         if (in.idx) {
             uint8_t* dst = DIR == 0 ? in.idx + ((gl * (n + 1) + face) * NV) * 2
@@ -651,7 +663,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const int v = gvar(q);
-            double L = -((sm.F[q][tl * TF + tf + 1] - sm.F[q][tl * TF + tf]) * in.ih);
+            double L = -((sm.F[q][fpos(tl, tf + 1)] - sm.F[q][fpos(tl, tf)]) * in.ih);
             if (so.Lprev) L = so.Lprev[v * plane + g] + L;
             if (so.stage == 0) so.out[v * plane + g] = L;
             else so.out[v * plane + g] = rk_combine(so.stage, so.Un[v * plane + g], in.Us[v * plane + g], L, dt);
@@ -659,13 +671,37 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     }
 }
 
+// Workgroups are handed to the XCDs round-robin by linear id, and each XCD has
+// its own L2.  The linear id is remapped so that every XCD takes runs of
+// kXcdRun consecutive tiles, ordered with the tiles that share cache lines
+// next to each other: along the line for x faces (shared halo cells), across
+// lines for y faces (the lines of neighbouring tiles are neighbouring columns
+// of the same rows).  Short runs keep the XCDs' shares of the domain
+// interleaved, so the non-smooth regions spread evenly over them.
+constexpr unsigned kXcds = 8, kXcdRun = 4;
+
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb)
+{
+    constexpr unsigned G = kXcds * kXcdRun;
+    const unsigned g = b / G;
+    if ((g + 1) * G > nb) return b;   // last partial group: identity
+    const unsigned r = b - g * G;
+    return g * G + (r % kXcds) * kXcdRun + r / kXcds;
+}
+
+// One tile per workgroup, 1D grid of ceil(n / (TF-1)) x ceil(nlines / TL) tiles.
 template <int NV, int R, int DIR, int TF, int TL>
 __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut so)
 {
     if (in.active && *in.active == 0) return;
     constexpr int NCL = TF + 2 * R - 1;
     __shared__ SweepLds<NV, NCL * TL, TF * TL> lds;
-    sweep_tile<NV, R, DIR, TF, TL, NCL>(in, so, (long)blockIdx.y * TL, (long)blockIdx.x * (TF - 1), lds);
+    const long n = DIR == 0 ? in.nx : in.ny, nlines = DIR == 0 ? in.ny : in.nx;
+    const unsigned nft = (unsigned)((n + TF - 2) / (TF - 1)), nlt = (unsigned)((nlines + TL - 1) / TL);
+    const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
+    const unsigned ft = DIR == 0 ? t % nft : t / nlt;
+    const unsigned lt = DIR == 0 ? t / nft : t % nlt;
+    sweep_tile<NV, R, DIR, TF, TL, NCL>(in, so, (long)lt * TL, (long)ft * (TF - 1), lds);
 }
 
 // ---------------------------------------------------------------------------

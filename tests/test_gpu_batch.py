@@ -58,6 +58,33 @@ def test_batch_equals_single_problem_runs_bitwise(ctx):
     batch.close()
 
 
+@pytest.mark.parametrize("tf", [64, 128, 256])
+def test_batch_multi_tile_problems_each_width(ctx, tf):
+    # Problems of many tiles each: a workgroup runs tile after tile on the same
+    # LDS, so every width (1, 2 and 4 waves) must equal the single-problem runs.
+    import torch
+    import paper_2311_15504_amd as enomr
+    rng = np.random.default_rng(tf)
+    probs, data = [], []
+    for i in range(12):
+        order = int(rng.choice([7, 9, 13, 17]))
+        n = int(rng.integers(1500, 4000))
+        _, h, U = workloads.euler1d_riemann_perturbed(5000 + tf + i, n)
+        probs.append(enomr.Problem.euler1d(n, h, order))
+        data.append(U)
+    states = [torch.from_numpy(U).cuda() for U in data]
+    batch = enomr.Batch(ctx, probs, states, tile_faces=tf)
+    assert batch.info()["tile_faces"] == tf
+    batch.advance(0.5, 20)
+    ctx.check()
+    for p, U0, Ub in zip(probs, data, states):
+        Us = torch.from_numpy(U0).cuda()
+        ctx.advance(p, Us, 0.5, 20)
+        ctx.check()
+        assert torch.equal(Ub, Us), (tf, p.nx, p.order)
+    batch.close()
+
+
 def test_batch_matches_oracle(ctx):
     import torch
     import paper_2311_15504_amd as enomr
@@ -81,3 +108,7 @@ def test_batch_rejects_bad_problems(ctx):
     p2 = enomr.Problem.euler2d(32, 32, hx, hy, 5)
     with pytest.raises(enomr.EnomrError):
         enomr.Batch(ctx, [p2], [torch.from_numpy(U2).cuda()])
+    _, h, U1 = workloads.euler1d_riemann_perturbed(0, 100)
+    p1 = enomr.Problem.euler1d(100, h, 9)
+    with pytest.raises(enomr.EnomrError):
+        enomr.Batch(ctx, [p1], [torch.from_numpy(U1).cuda()], tile_faces=96)
