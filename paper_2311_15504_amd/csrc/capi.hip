@@ -15,7 +15,6 @@
 
 namespace enomr {
 __constant__ double c_a[kPool][kMaxW];
-__constant__ double c_b[kPool][kMaxW];
 __constant__ double c_wa[2][kPool][kMaxW];
 __constant__ int c_candpool[10][kPool];
 }  // namespace enomr
@@ -485,7 +484,6 @@ enomr_status enomr_create(int device, void* hip_stream, enomr_ctx** out)
     for (int R = 0; R < 10; ++R)
         for (int c = 0; c < kPool; ++c) cp[R][c] = (R >= 3 && c < n_cands(R)) ? cand_pool(R, c) : 0;
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_a), ta, sizeof(ta)));
-    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_b), tb, sizeof(tb)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_wa), wa, sizeof(wa)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_candpool), cp, sizeof(cp)));
     enomr_ctx* c = new enomr_ctx;

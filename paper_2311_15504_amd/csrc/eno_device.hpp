@@ -16,9 +16,9 @@
 
 namespace enomr {
 
-// a_l and b_l of every pool stencil, entry l+m (filled at context creation).
+// a_l of every pool stencil, entry l+m, for runtime-indexed use (filled at
+// context creation; compile-time positions read kCoef instead).
 extern __constant__ double c_a[kPool][kMaxW];
-extern __constant__ double c_b[kPool][kMaxW];
 
 // The a_l aligned to a 17-entry window centred at entry 8 and zero outside
 // the stencil: c_wa[s][P][i] multiplies window entry i for sign s (0: +,
@@ -92,33 +92,35 @@ __device__ __forceinline__ double minmod_flux(const double (&w)[2 * R - 1], int&
 // (m+n)-th derivative of the stencil polynomial; Table ISCoe holds its binomial
 // expansion), taken by repeated differencing of the window in ascending cell
 // order.  One difference table of the window, built level by level in place,
-// yields every candidate's indicator; each candidate's pass bit is recorded at
-// its level and the lowest set bit is the first passing candidate in list
+// yields every candidate's indicator.  Levels are built upwards while list
+// order runs downwards in level, so a passing candidate overwrites the choice
+// made at lower levels, and within a level the candidates are visited in
+// reverse list order: the last write is the first passing candidate in list
 // order.  In the sign's frame stencil (m, n) starts at window entry R-1-m
 // (f^+) or R-1-n (f^-, the mirror image).
 template <int R, int S, int LEV, int C>
-__device__ __forceinline__ void mark_level(const double (&d)[2 * R - 1], double is0, unsigned& pass)
+__device__ __forceinline__ void mark_level(const double (&d)[2 * R - 1], double is0, int& chosen)
 {
-    if constexpr (C < n_cands(R)) {
+    if constexpr (C >= 1) {
         constexpr int P = cand_pool(R, C);
         constexpr int m = pool_mn(P, 0), n = pool_mn(P, 1);
         if constexpr (m >= 1 && n >= 1 && m + n == LEV) {
             constexpr int s = S > 0 ? R - 1 - m : R - 1 - n;
-            if (fabs(d[s]) < is0) pass |= 1u << C;
+            chosen = fabs(d[s]) < is0 ? C : chosen;
         }
-        mark_level<R, S, LEV, C + 1>(d, is0, pass);
+        mark_level<R, S, LEV, C - 1>(d, is0, chosen);
     }
 }
 
 template <int R, int S, int LEV>
-__device__ __forceinline__ void difference_levels(double (&d)[2 * R - 1], double is0, unsigned& pass)
+__device__ __forceinline__ void difference_levels(double (&d)[2 * R - 1], double is0, int& chosen)
 {
     // the full stencil's level 2R-2 is not needed: candidate 0 is tested by its b_l chain
     if constexpr (LEV <= 2 * R - 3) {
 #pragma unroll
         for (int i = 0; i + LEV < 2 * R - 1; ++i) d[i] = d[i + 1] - d[i];
-        mark_level<R, S, LEV, 1>(d, is0, pass);
-        difference_levels<R, S, LEV + 1>(d, is0, pass);
+        mark_level<R, S, LEV, n_cands(R) - 1>(d, is0, chosen);
+        difference_levels<R, S, LEV + 1>(d, is0, chosen);
     }
 }
 
@@ -127,9 +129,9 @@ __device__ __forceinline__ void difference_levels(double (&d)[2 * R - 1], double
 template <int R, int S>
 __device__ __forceinline__ int first_passing(double (&d)[2 * R - 1], double is0)
 {
-    unsigned pass = 0;
-    difference_levels<R, S, 1>(d, is0, pass);
-    return pass ? __builtin_ctz(pass) : -1;
+    int chosen = -1;
+    difference_levels<R, S, 1>(d, is0, chosen);
+    return chosen;
 }
 
 // The flux of candidate c over the window: padded window-aligned a_l row.
@@ -164,9 +166,9 @@ __device__ __forceinline__ double recon(const double (&w)[2 * R - 1], int& idx)
 {
     constexpr int P0 = cand_pool(R, 0);
     const double is0 = baseline_is<R, S>(w);
-    if (fabs(sdot<R, S, P0>(c_b[P0], w)) < is0) {
+    if (fabs(sdot<R, S, P0>(kCoef.b[P0], w)) < is0) {
         idx = 0;
-        return sdot<R, S, P0>(c_a[P0], w);
+        return sdot<R, S, P0>(kCoef.a[P0], w);
     }
     return select_rest<R, S>(w, is0, idx);
 }

@@ -329,31 +329,20 @@ __device__ __forceinline__ void project(const Eig& e, const double (&G)[NV], dou
     }
 }
 
-// Row k of L as a generic chain (slow path; k is uniform across the wave).
-template <int NV>
-__device__ __forceinline__ void l_row(const Eig& e, int k, double (&r)[NV])
+// Field Q of L G, the same chain as project<NV> computes for it.
+template <int NV, int Q>
+__device__ __forceinline__ double project_row(const Eig& e, const double (&G)[NV])
 {
     if constexpr (NV == 4) {
-        const bool f0 = k == 0, f1 = k == 1, f2 = k == 2;
-        r[0] = f0 ? e.a0 : (f1 ? e.l20 : (f2 ? -e.v : e.a3));
-        r[1] = f0 ? e.a1 : (f1 ? e.ku : (f2 ? 0.0 : e.a4));
-        r[2] = f0 ? e.C : (f1 ? e.kv : (f2 ? 1.0 : e.C));
-        r[3] = f0 ? e.D : (f1 ? -e.k : (f2 ? 0.0 : e.D));
+        if constexpr (Q == 0) return fma(e.D, G[3], fma(e.C, G[2], fma(e.a1, G[1], e.a0 * G[0])));
+        if constexpr (Q == 1) return fma(-e.k, G[3], fma(e.kv, G[2], fma(e.ku, G[1], e.l20 * G[0])));
+        if constexpr (Q == 2) return (-e.v) * G[0] + G[2];
+        return fma(e.D, G[3], fma(e.C, G[2], fma(e.a4, G[1], e.a3 * G[0])));
     } else {
-        const bool f0 = k == 0, f1 = k == 1;
-        r[0] = f0 ? e.a0 : (f1 ? e.l20 : e.a3);
-        r[1] = f0 ? e.a1 : (f1 ? e.ku : e.a4);
-        r[2] = f0 ? e.D : (f1 ? -e.k : e.D);
+        if constexpr (Q == 0) return fma(e.D, G[2], fma(e.a1, G[1], e.a0 * G[0]));
+        if constexpr (Q == 1) return fma(-e.k, G[2], fma(e.ku, G[1], e.l20 * G[0]));
+        return fma(e.D, G[2], fma(e.a4, G[1], e.a3 * G[0]));
     }
-}
-
-template <int NV>
-__device__ __forceinline__ double row_chain(const double (&r)[NV], const double (&G)[NV])
-{
-    double acc = r[0] * G[0];
-#pragma unroll
-    for (int q = 1; q < NV; ++q) acc = fma(r[q], G[q], acc);
-    return acc;
 }
 
 // F-hat = R w-hat, chains over fields 0..NV-1.
@@ -395,6 +384,37 @@ struct SweepLds {
     double Ut[NV == 4 ? NCELL : 1];
     double F[NV][NFACE];
 };
+
+// Steps 3.1/3.2 beyond the full stencil for field Q and sign S at one face:
+// project the sign's window (ascending cells, LDS entries lp0 + i*STEP),
+// build its difference table in place, and evaluate the chosen candidate's
+// flux chain on a second projection of the window (bitwise the same values;
+// re-projecting is cheaper than holding the window in registers).
+template <int NV, int R, int S, int Q, int STEP, int NCELL>
+__device__ __forceinline__ double fallback_window(const Eig& e, const double (&G)[NV][NCELL], int lp0, int& id)
+{
+    constexpr int W = 2 * R - 1;
+    auto proj = [&](int i) {
+        double g[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) g[c] = G[c][lp0 + i * STEP];
+        return project_row<NV, Q>(e, g);
+    };
+    double w[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = proj(i);
+    const double f0 = w[R - 1], lo = w[R - 2], hi = w[R];
+    const int c = first_passing<R, S>(w, baseline_is<R, S>(w));
+    if (c >= 0) {
+        const double* wa = &c_wa[S > 0 ? 0 : 1][c_candpool[R][c]][9 - R];
+        double f = wa[0] * proj(0);
+#pragma unroll
+        for (int i = 1; i < W; ++i) f = fma(wa[i], proj(i), f);
+        id = c;
+        return f;
+    }
+    return S > 0 ? minmod3<R>(f0, hi, lo, id) : minmod3<R>(f0, lo, hi, id);
+}
 
 // One tile of the characteristic ENO-MR sweep: lines line0 .. line0+TL-1,
 // faces c0 .. c0+TF-1 (cells c0 .. c0+TF-2).  DIR 0: lines are rows (x faces);
@@ -497,11 +517,11 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
 #pragma unroll
                 for (int q = 0; q < NV; ++q) {
                     if (o == -R + 1) {
-                        is[q] = c_b[P0][ci] * w[q];
-                        fl[q] = c_a[P0][ci] * w[q];
+                        is[q] = kCoef.b[P0][ci] * w[q];
+                        fl[q] = kCoef.a[P0][ci] * w[q];
                     } else {
-                        is[q] = fma(c_b[P0][ci], w[q], is[q]);
-                        fl[q] = fma(c_a[P0][ci], w[q], fl[q]);
+                        is[q] = fma(kCoef.b[P0][ci], w[q], is[q]);
+                        fl[q] = fma(kCoef.a[P0][ci], w[q], fl[q]);
                     }
                     if (o == -2) a[q] = w[q];
                     if (o == -1) b[q] = w[q];
@@ -549,11 +569,11 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
 #pragma unroll
                 for (int q = 0; q < NV; ++q) {
                     if (o == -R + 2) {
-                        is[q] = c_b[P0][ci] * w[q];
-                        fl[q] = c_a[P0][ci] * w[q];
+                        is[q] = kCoef.b[P0][ci] * w[q];
+                        fl[q] = kCoef.a[P0][ci] * w[q];
                     } else {
-                        is[q] = fma(c_b[P0][ci], w[q], is[q]);
-                        fl[q] = fma(c_a[P0][ci], w[q], fl[q]);
+                        is[q] = fma(kCoef.b[P0][ci], w[q], is[q]);
+                        fl[q] = fma(kCoef.a[P0][ci], w[q], fl[q]);
                     }
                     if (o == -1) a[q] = w[q];
                     if (o == 0) b[q] = w[q];
@@ -586,54 +606,35 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             }
         }
 
-        // ---- remaining candidates for the (field, sign) pairs that failed
+        constexpr int LSTEP = DIR == 0 ? 1 : TL;   // LDS step between neighbouring cells of a line
+        // ---- remaining candidates for the (field, sign) pairs that failed;
+        // the pair index is uniform across the wave, so each pass runs code
+        // specialised to its field and sign
         if (fail) {
 #pragma unroll 1
             for (int kk = 0; kk < 2 * NV; ++kk) {
                 if (!((fail >> kk) & 1u)) continue;
-                const int q = kk >> 1;
-                double r[NV];
-                l_row<NV>(e, q, r);
-                // project the window (ascending cells), keep what minmod needs,
-                // then turn the window into its difference table
-                const int base = (kk & 1) == 0 ? jp - (R - 1) : jp - (R - 2);
-                auto proj = [&](int i) {
-                    const int lp = lpos(tl, base + i);
-                    double G[NV];
-                    if ((kk & 1) == 0) {
-#pragma unroll
-                        for (int c = 0; c < NV; ++c) G[c] = sm.Gp[c][lp];
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < NV; ++c) G[c] = sm.Gm[c][lp];
-                    }
-                    return row_chain<NV>(r, G);
-                };
-                double w[W];
-#pragma unroll
-                for (int i = 0; i < W; ++i) w[i] = proj(i);
                 int id;
                 double res;
-                const double f0 = w[R - 1], lo = w[R - 2], hi = w[R];
-                int c;
-                if ((kk & 1) == 0) c = first_passing<R, +1>(w, baseline_is<R, +1>(w));
-                else c = first_passing<R, -1>(w, baseline_is<R, -1>(w));
-                if (c >= 0) {
-                    // re-project (bitwise the same values) into the chosen row
-                    const double* wa = &c_wa[kk & 1][c_candpool[R][c]][9 - R];
-                    res = wa[0] * proj(0);
-#pragma unroll 1
-                    for (int i = 1; i < W; ++i) res = fma(wa[i], proj(i), res);
-                    id = c;
-                } else {
-                    res = (kk & 1) == 0 ? minmod3<R>(f0, hi, lo, id) : minmod3<R>(f0, lo, hi, id);
-                }
-#pragma unroll
-                for (int t = 0; t < NV; ++t) {
-                    if (t == q) {
-                        if ((kk & 1) == 0) hp[t] = res;
-                        else hm[t] = res;
+                switch (kk) {
+                case 0: res = fallback_window<NV, R, +1, 0, LSTEP, NCL * TL>(e, sm.Gp, lpos(tl, jp - (R - 1)), id); hp[0] = res; break;
+                case 1: res = fallback_window<NV, R, -1, 0, LSTEP, NCL * TL>(e, sm.Gm, lpos(tl, jp - (R - 2)), id); hm[0] = res; break;
+                case 2: res = fallback_window<NV, R, +1, 1, LSTEP, NCL * TL>(e, sm.Gp, lpos(tl, jp - (R - 1)), id); hp[1] = res; break;
+                case 3: res = fallback_window<NV, R, -1, 1, LSTEP, NCL * TL>(e, sm.Gm, lpos(tl, jp - (R - 2)), id); hm[1] = res; break;
+                case 4: res = fallback_window<NV, R, +1, 2, LSTEP, NCL * TL>(e, sm.Gp, lpos(tl, jp - (R - 1)), id); hp[2] = res; break;
+                case 5: res = fallback_window<NV, R, -1, 2, LSTEP, NCL * TL>(e, sm.Gm, lpos(tl, jp - (R - 2)), id); hm[2] = res; break;
+                case 6:
+                    if constexpr (NV == 4) {
+                        res = fallback_window<NV, R, +1, 3, LSTEP, NCL * TL>(e, sm.Gp, lpos(tl, jp - (R - 1)), id);
+                        hp[3] = res;
                     }
+                    break;
+                default:
+                    if constexpr (NV == 4) {
+                        res = fallback_window<NV, R, -1, 3, LSTEP, NCL * TL>(e, sm.Gm, lpos(tl, jp - (R - 2)), id);
+                        hm[3] = res;
+                    }
+                    break;
                 }
                 idxw |= (uint64_t)(uint8_t)id << (8 * kk);
             }
@@ -653,20 +654,31 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             for (int b = 0; b < 2 * NV; ++b) dst[b] = (uint8_t)(idxw >> (8 * b));
         }
     }
-    __syncthreads();
-
-    // ---- conservative difference and output
+    // ---- conservative difference and output; the cell's operands are
+    // requested before the barrier so that their latency overlaps it
     const long cell = c0 + tf;
-    if (gl < nlines && tf < TC && cell < n) {
-        const long g = gidx(gl, cell);
+    const bool outc = gl < nlines && tf < TC && cell < n;
+    const long g = outc ? gidx(gl, cell) : 0;
+    double lp[NV], un[NV], us[NV];
+    if (outc) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const long i = gvar(q) * plane + g;
+            lp[q] = so.Lprev ? so.Lprev[i] : 0.0;
+            un[q] = so.stage ? so.Un[i] : 0.0;
+            us[q] = so.stage ? in.Us[i] : 0.0;
+        }
+    }
+    __syncthreads();
+    if (outc) {
         const double dt = so.stage ? *so.dt : 0.0;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const int v = gvar(q);
             double L = -((sm.F[q][fpos(tl, tf + 1)] - sm.F[q][fpos(tl, tf)]) * in.ih);
-            if (so.Lprev) L = so.Lprev[v * plane + g] + L;
+            if (so.Lprev) L = lp[q] + L;
             if (so.stage == 0) so.out[v * plane + g] = L;
-            else so.out[v * plane + g] = rk_combine(so.stage, so.Un[v * plane + g], in.Us[v * plane + g], L, dt);
+            else so.out[v * plane + g] = rk_combine(so.stage, un[q], us[q], L, dt);
         }
     }
 }

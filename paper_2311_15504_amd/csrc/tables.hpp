@@ -52,8 +52,110 @@ __host__ __device__ constexpr int cand_pool(int R, int C)
     return -1;
 }
 
-// Host-side generation of a_l and b_l for every pool stencil, as doubles
-// nearest to the exact rationals.  a[c][l+m], b[c][l+m].
+// a_l and b_l of every pool stencil, a[c][l+m], b[c][l+m], generated at
+// compile time in exact rational arithmetic and rounded to the nearest
+// doubles.  Kernels index the table with compile-time positions, so the
+// coefficients become instruction immediates.
+namespace coefgen {
+
+typedef __int128 i128;
+
+constexpr i128 iabs(i128 x) { return x < 0 ? -x : x; }
+
+constexpr i128 gcd(i128 a, i128 b)
+{
+    a = iabs(a);
+    b = iabs(b);
+    while (b != 0) {
+        const i128 t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+struct Rat {
+    i128 p, q;   // q > 0, reduced
+};
+
+constexpr Rat make(i128 p, i128 q)
+{
+    if (q < 0) { p = -p; q = -q; }
+    i128 g = gcd(p, q);
+    if (g == 0) g = 1;
+    return Rat{p / g, q / g};
+}
+
+constexpr Rat add(Rat x, Rat y) { return make(x.p * y.q + y.p * x.q, x.q * y.q); }
+
+// Derivative at interface node s of the Lagrange basis polynomial of node q,
+// nodes at the integers 0..K (unit spacing).
+constexpr Rat basis_derivative(int q, int s, int K)
+{
+    if (q != s) {
+        i128 num = 1, den = 1;
+        for (int t = 0; t <= K; ++t) {
+            if (t != q && t != s) num *= (s - t);
+            if (t != q) den *= (q - t);
+        }
+        return make(num, den);
+    }
+    Rat acc = make(0, 1);
+    for (int t = 0; t <= K; ++t)
+        if (t != s) acc = add(acc, make(1, s - t));
+    return acc;
+}
+
+constexpr i128 binom(int n, int k)
+{
+    i128 r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+// Reduced numerators and denominators stay below 2^53 (checked when the
+// table is built), so both convert exactly and one IEEE division rounds the
+// quotient correctly.
+constexpr double to_double(Rat x) { return (double)(long long)x.p / (double)(long long)x.q; }
+constexpr bool fits(Rat x) { return iabs(x.p) < (((i128)1) << 53) && x.q < (((i128)1) << 53); }
+
+struct CoefTable {
+    double a[kPool][kMaxW];
+    double b[kPool][kMaxW];
+    bool exact;   // every rational converted exactly before rounding
+};
+
+constexpr CoefTable make_table()
+{
+    CoefTable t{};
+    t.exact = true;
+    for (int c = 0; c < kPool; ++c) {
+        const int m = pool_mn(c, 0), n = pool_mn(c, 1);
+        const int K = m + n + 1;   // interfaces x_{j-m-1/2} .. x_{j+n+1/2} -> nodes 0..K
+        const int s = m + 1;       // x_{j+1/2}
+        Rat d[kMaxW + 2] = {};
+        for (int q = 0; q <= K; ++q) d[q] = basis_derivative(q, s, K);
+        for (int i = 0; i < K; ++i) {
+            // a_i: sum over interfaces right of cell i of the basis derivatives
+            Rat acc = make(0, 1);
+            for (int q = i + 1; q <= K; ++q) acc = add(acc, d[q]);
+            t.exact = t.exact && fits(acc);
+            t.a[c][i] = to_double(acc);
+            const int deg = m + n;
+            i128 bv = binom(deg, i);
+            if ((deg - i) % 2) bv = -bv;
+            t.b[c][i] = (double)(long long)bv;
+        }
+    }
+    return t;
+}
+
+}  // namespace coefgen
+
+inline constexpr coefgen::CoefTable kCoef = coefgen::make_table();
+static_assert(kCoef.exact, "a coefficient's numerator or denominator exceeds 2^53");
+
+// Host copies of the table (a[c][l+m], b[c][l+m]).
 bool generate_tables(double a[kPool][kMaxW], double b[kPool][kMaxW]);
 
 }  // namespace enomr
