@@ -12,6 +12,7 @@ oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -111,6 +112,11 @@ def run(args):
     cells = n * n
     value = cells * 3 * args.steps / (ms * 1e-3)
 
+    if args.no_replay:
+        ctx.close()
+        return {"metric": METRIC, "value": value, "unit": "cell-updates/s", "ms_per_step": ms / args.steps,
+                "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()}, "roofline": None}
+
     # algorithmic work of the same K steps: replay them (bitwise identical)
     # with stencil logs and count what each face needed.
     U.copy_(U0d)
@@ -166,7 +172,7 @@ def run(args):
                                "x periodic / y outflow, seeded quadrants + 8 isentropic vortices" % (n, n, order),
                    "nx": n, "ny": n, "order": order, "cfl": cfl, "seed": args.seed},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": recorded_traffic(dom), "kernel": dom,
                      "algorithmic_flop_per_launch": per_launch, "avg_launch_ms": avg_ms},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
         "full_stencil_fraction": {"x": smooth_frac_x, "y": smooth_frac_y},
@@ -285,6 +291,98 @@ def run_adjoint(args):
             "cell_updates_per_s_forward": n * 3 * nsteps / (t_fwd * 1e-3), "gradient_finite": ok}
 
 
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "k_euler_sweep_2d_2048_order17_traffic.md")
+
+
+def sweep_source_hash():
+    """sha256 of the library sources; a recorded traffic figure is used only
+    while the kernels are the ones it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2311_15504_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_MD) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256") != sweep_source_hash():
+        return None
+    return rec.get("bytes_per_launch", {}).get(kernel)
+
+
+def traffic_summary(fetch_dir, write_dir, copy_mib, command):
+    """Per-launch HBM bytes of the two sweeps from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch, summed over the counter's instances),
+    each scaled by what the same counter reads for torch's copy of copy_mib
+    MiB (the calibration copy of --calib-copy-mib)."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter):
+        # sweeps: mean over their dispatches; copy: the largest copy-kernel
+        # dispatch, which is the calibration copy
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                if row["Counter_Name"] != counter:
+                    continue
+                k = row["Kernel_Name"]
+                if "k_euler_sweep<4" in k:
+                    key = "k_euler_sweep (x faces)" if ", 0, " in k else "k_euler_sweep (y faces)"
+                elif "copyBuffer" in k:
+                    key = "copy"
+                else:
+                    continue
+                per = vals.setdefault(key, {})
+                per[row["Dispatch_Id"]] = per.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+        out = {k: sum(v.values()) / len(v) for k, v in vals.items() if k != "copy"}
+        out["copy"] = max(vals["copy"].values())
+        return out
+
+    fe = per_dispatch(fetch_dir, "FETCH_SIZE")
+    wr = per_dispatch(write_dir, "WRITE_SIZE")
+    kib = copy_mib * 1024.0
+    f_fetch, f_write = kib / fe["copy"], kib / wr["copy"]
+    out = {}
+    for k in ("k_euler_sweep (x faces)", "k_euler_sweep (y faces)"):
+        out[k] = (fe[k] * f_fetch + wr[k] * f_write) * 1024.0
+    rec = {"source_sha256": sweep_source_hash(), "bytes_per_launch": out,
+           "fetch_kib_per_dispatch": fe, "write_kib_per_dispatch": wr,
+           "calibration": {"copy_mib": copy_mib, "fetch_scale": f_fetch, "write_scale": f_write}}
+    lines = ["# HBM traffic: 2D Euler 2048x2048, ENO-MR order 17, sweep kernels", "",
+             "Commands (repository root, one MI355X; `cd /tmp && export TMPDIR=/tmp` first):", "", "```",
+             command, "```", "",
+             "FETCH_SIZE and WRITE_SIZE are KiB per dispatch summed over the counter's instances. Each is scaled",
+             "by the factor that maps the same counter, read on the copy kernel that torch's copy of a %d MiB" % copy_mib,
+             "float64 tensor launches in the",
+             "same run, to the %d MiB that copy reads and writes." % copy_mib, "",
+             "| kernel | FETCH KiB/launch | WRITE KiB/launch | HBM bytes/launch (scaled) |", "|---|---|---|---|"]
+    for k in ("k_euler_sweep (x faces)", "k_euler_sweep (y faces)", "copy"):
+        b = out.get(k, (fe[k] * f_fetch + wr[k] * f_write) * 1024.0)
+        lines.append("| %s | %.0f | %.0f | %.4g |" % (k, fe[k], wr[k], b))
+    n2 = 2048 * 2048 * 4 * 8
+    lines += ["", "Scale factors: fetch %.4f, write %.4f." % (f_fetch, f_write), "",
+              "Compulsory bytes per launch: x sweep %.4g (read U_s, write L_x); y sweep %.4g (read U_s, L_x," % (2 * n2, 4 * n2),
+              "U^n, write the stage state; %.4g at the first stage, where U_s is U^n)." % (3 * n2), "",
+              "bench.py reads the record below and reports `roofline.traffic` for the dominant sweep while",
+              "`source_sha256` matches the library sources (null otherwise).", "", "```json",
+              json.dumps(rec, indent=1), "```", ""]
+    return "\n".join(lines)
+
+
 def cpu_baseline(args):
     """The oracle (single thread) on a 512 x 512 window of the same initial state, one step."""
     import oracle
@@ -319,7 +417,18 @@ def main():
     ap.add_argument("--batch-sample", type=int, default=64)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--no-replay", action="store_true",
+                    help="skip the stencil-logged replay that counts algorithmic work (counter runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a float64 tensor of this many MiB (counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
+                    help="write the traffic summary from two rocprofv3 counter runs to stdout and exit")
+    ap.add_argument("--traffic-command", default="", help="command text recorded in the summary")
     args = ap.parse_args()
+    if args.traffic_summary:
+        fd, wd, mib = args.traffic_summary
+        print(traffic_summary(fd, wd, int(mib), args.traffic_command))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -329,6 +438,12 @@ def main():
     out["batched"] = None if args.no_batched else run_batched(args)
     out["adjoint"] = None if args.no_adjoint else run_adjoint(args)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args)
+    if args.calib_copy_mib:
+        import torch
+        src = torch.ones(args.calib_copy_mib * 131072, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 
