@@ -24,8 +24,14 @@ enum { SYS_ADVECTION = 0, SYS_BURGERS = 1 };
 __device__ __forceinline__ long map_cell(long i, long n, int bc)
 {
     if (bc == BC_PERIODIC) {
-        long k = i % n;
-        return k < 0 ? k + n : k;
+        // callers stay within a few tiles of the line, so one wrap is the
+        // rule; the division is only reached on lines shorter than a tile
+        long k = i < 0 ? i + n : (i >= n ? i - n : i);
+        if (k < 0 || k >= n) {
+            k = i % n;
+            if (k < 0) k += n;
+        }
+        return k;
     }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }

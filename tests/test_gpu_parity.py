@@ -199,6 +199,29 @@ def test_euler2d_riemann_configurations(ctx):
             assert np.array_equal(_host(got), ref)
 
 
+@pytest.mark.parametrize("order", [9, 17])
+def test_smallest_periodic_grids_wrap_many_times(ctx, order):
+    # n = 2r + 1 periodic: a 63-cell tile stages cells several periods away,
+    # which takes the index map's general (division) branch.
+    import paper_2311_15504_amd as enomr
+    n = order + 2
+    (x, y, hx, hy), U = workloads.euler2d_quadrants_vortices(order, n, n)
+    ref, ix, iy, _, _ = oracle.euler2d_rhs(order, U, hx, hy, bcx=oracle.PERIODIC, bcy=oracle.PERIODIC,
+                                         with_idx=True)
+    prob = enomr.Problem.euler2d(n, n, hx, hy, order, enomr.PERIODIC, enomr.PERIODIC)
+    got, gidx = ctx.rhs(prob, _dev(U), with_idx=True)
+    ctx.check()
+    gidx = _host(gidx)
+    nxf = n * (n + 1) * 8
+    assert np.array_equal(gidx[:nxf].reshape(n, n + 1, 4, 2), ix)
+    assert np.array_equal(gidx[nxf:].reshape(n + 1, n, 4, 2), iy)
+    assert np.array_equal(_host(got), ref)
+    _, h, u = workloads.advection_sines_step(order, n)
+    ref1 = oracle.scalar_rhs(order, u, h)
+    got1 = ctx.rhs(enomr.Problem.scalar(enomr.ADVECTION, n, h, order), _dev(u[None]))
+    assert np.array_equal(_host(got1)[0], ref1)
+
+
 def test_euler2d_run_matches_oracle(ctx):
     import paper_2311_15504_amd as enomr
     nx = ny = 64
