@@ -12,9 +12,11 @@
  * formula is part of the specification (the paper leaves it open); the GPU
  * kernels follow the same order so that stencil choices agree bit for bit.
  *
- *   - dot products (fluxes, projections, the full stencil's IS): first term a
+ *   - dot products (fluxes, the full stencil's IS, R w-hat): first term a
  *     plain product, then fma() terms, in ascending physical cell (or
  *     component) order;
+ *   - projections L G: the same chain from the last component to the first
+ *     (rows u-c and u+c then share their last two terms);
  *   - IS of every other candidate: the (m+n)-th undivided difference of its
  *     cells in ascending order, by repeated differencing f_{i+1} - f_i;
  *   - IS0 second differences: (f_c - 2 f_{c-1}) + f_{c-2};
@@ -392,6 +394,14 @@ static double row_dot(const double *row, const double *x, int nv)
     return acc;
 }
 
+/* A row of L applied to a split flux: the chain from the last component down. */
+static double project_dot(const double *row, const double *x, int nv)
+{
+    double acc = row[nv - 1] * x[nv - 1];
+    for (int i = nv - 2; i >= 0; --i) acc = fma(row[i], x[i], acc);
+    return acc;
+}
+
 /*
  * Largest characteristic speed |u_n| + c over the n cells of a line
  * (alpha of Eq. LF_Flux_Split for the Euler system).
@@ -451,8 +461,8 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
         for (int k = 0; k < nv; ++k) {
             /* characteristic field k of the split fluxes over the face's window */
             for (long i = j - T->r + 1; i <= j + T->r; ++i) {
-                wp[i] = row_dot(Lm[k], &Gp[i * nv], nv);
-                wm[i] = row_dot(Lm[k], &Gm[i * nv], nv);
+                wp[i] = project_dot(Lm[k], &Gp[i * nv], nv);
+                wm[i] = project_dot(Lm[k], &Gm[i * nv], nv);
             }
             int kp, km;
             double hp = recon_face(T, wp, j, +1, &kp);
@@ -751,6 +761,14 @@ static dual ddot(const dual *c, const dual *x, int n)
     return acc;
 }
 
+/* project_dot() in dual arithmetic */
+static dual dproject(const dual *c, const dual *x, int n)
+{
+    dual acc = dmul(c[n - 1], x[n - 1]);
+    for (int i = n - 2; i >= 0; --i) acc = dfma(c[i], x[i], acc);
+    return acc;
+}
+
 /* recon of one window with a frozen choice k (frame as in recon_face) */
 static dual recon_frozen(const orc_table *T, const dual *f, long j, int sign, int k)
 {
@@ -850,8 +868,8 @@ int orc_euler1d_rhs_frozen(const orc_table *T, double gamma, int bc, long n, dou
         dual what[3];
         for (int q = 0; q < 3; ++q) {
             for (long i = j - T->r + 1; i <= j + T->r; ++i) {
-                wp[i] = ddot(Lm[q], &Gp[i * 3], 3);
-                wm[i] = ddot(Lm[q], &Gm[i * 3], 3);
+                wp[i] = dproject(Lm[q], &Gp[i * 3], 3);
+                wm[i] = dproject(Lm[q], &Gm[i * 3], 3);
             }
             int kp = idx[(f * 3 + q) * 2 + 0], km = idx[(f * 3 + q) * 2 + 1];
             if (kp >= T->ncand || km >= T->ncand) { st = ORC_EINVAL; goto done; }

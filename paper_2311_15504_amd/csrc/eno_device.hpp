@@ -49,7 +49,9 @@ __device__ __forceinline__ double sdot(const double* coef, const double (&w)[2 *
     return acc;
 }
 
-// Step 1: IS0 = min(IS_L, IS_R), Eq. (Baseline_IS).
+// Step 1: IS0 = min(IS_L, IS_R), Eq. (Baseline_IS).  The second differences
+// are (f0 - 2 f1) + f2; 2 f1 is exact, so fma(-2, f1, f0) rounds f0 - 2 f1
+// exactly as the subtraction does.
 template <int R, int S>
 __device__ __forceinline__ double baseline_is(const double (&w)[2 * R - 1])
 {
@@ -58,8 +60,8 @@ __device__ __forceinline__ double baseline_is(const double (&w)[2 * R - 1])
     const double fm2 = S > 0 ? w[R - 3] : w[R + 1];
     const double fp1 = S > 0 ? w[R] : w[R - 2];
     const double fp2 = S > 0 ? w[R + 1] : w[R - 3];
-    const double isl = fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2));
-    const double isr = fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2));
+    const double isl = fmax(fabs(f0 - fm1), fabs(fma(-2.0, fm1, f0) + fm2));
+    const double isr = fmax(fabs(f0 - fp1), fabs(fma(-2.0, fp1, f0) + fp2));
     return fmin(isl, isr);
 }
 

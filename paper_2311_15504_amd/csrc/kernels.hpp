@@ -317,21 +317,24 @@ __device__ __forceinline__ bool roe_eigen(double sL, double unL, double utL, dou
     return c2 > 0.0;
 }
 
-// w = L G for all fields; chains run over components 0..NV-1.  Structural
-// zeros of L are skipped and unit entries added (same value up to the sign
-// of a zero result).
+// w = L G for all fields.  Each row's chain runs from the last component to
+// the first (the rows u-c and u+c then share their last two terms).
+// Structural zeros of L are skipped and unit entries added (same value up to
+// the sign of a zero result).
 template <int NV>
 __device__ __forceinline__ void project(const Eig& e, const double (&G)[NV], double (&w)[NV])
 {
     if constexpr (NV == 4) {
-        w[0] = fma(e.D, G[3], fma(e.C, G[2], fma(e.a1, G[1], e.a0 * G[0])));
-        w[1] = fma(-e.k, G[3], fma(e.kv, G[2], fma(e.ku, G[1], e.l20 * G[0])));
-        w[2] = (-e.v) * G[0] + G[2];
-        w[3] = fma(e.D, G[3], fma(e.C, G[2], fma(e.a4, G[1], e.a3 * G[0])));
+        const double t = fma(e.C, G[2], e.D * G[3]);
+        w[0] = fma(e.a0, G[0], fma(e.a1, G[1], t));
+        w[1] = fma(e.l20, G[0], fma(e.ku, G[1], fma(e.kv, G[2], (-e.k) * G[3])));
+        w[2] = fma(-e.v, G[0], G[2]);
+        w[3] = fma(e.a3, G[0], fma(e.a4, G[1], t));
     } else {
-        w[0] = fma(e.D, G[2], fma(e.a1, G[1], e.a0 * G[0]));
-        w[1] = fma(-e.k, G[2], fma(e.ku, G[1], e.l20 * G[0]));
-        w[2] = fma(e.D, G[2], fma(e.a4, G[1], e.a3 * G[0]));
+        const double t = e.D * G[2];
+        w[0] = fma(e.a0, G[0], fma(e.a1, G[1], t));
+        w[1] = fma(e.l20, G[0], fma(e.ku, G[1], (-e.k) * G[2]));
+        w[2] = fma(e.a3, G[0], fma(e.a4, G[1], t));
     }
 }
 
@@ -340,14 +343,14 @@ template <int NV, int Q>
 __device__ __forceinline__ double project_row(const Eig& e, const double (&G)[NV])
 {
     if constexpr (NV == 4) {
-        if constexpr (Q == 0) return fma(e.D, G[3], fma(e.C, G[2], fma(e.a1, G[1], e.a0 * G[0])));
-        if constexpr (Q == 1) return fma(-e.k, G[3], fma(e.kv, G[2], fma(e.ku, G[1], e.l20 * G[0])));
-        if constexpr (Q == 2) return (-e.v) * G[0] + G[2];
-        return fma(e.D, G[3], fma(e.C, G[2], fma(e.a4, G[1], e.a3 * G[0])));
+        if constexpr (Q == 0) return fma(e.a0, G[0], fma(e.a1, G[1], fma(e.C, G[2], e.D * G[3])));
+        if constexpr (Q == 1) return fma(e.l20, G[0], fma(e.ku, G[1], fma(e.kv, G[2], (-e.k) * G[3])));
+        if constexpr (Q == 2) return fma(-e.v, G[0], G[2]);
+        return fma(e.a3, G[0], fma(e.a4, G[1], fma(e.C, G[2], e.D * G[3])));
     } else {
-        if constexpr (Q == 0) return fma(e.D, G[2], fma(e.a1, G[1], e.a0 * G[0]));
-        if constexpr (Q == 1) return fma(-e.k, G[2], fma(e.ku, G[1], e.l20 * G[0]));
-        return fma(e.D, G[2], fma(e.a4, G[1], e.a3 * G[0]));
+        if constexpr (Q == 0) return fma(e.a0, G[0], fma(e.a1, G[1], e.D * G[2]));
+        if constexpr (Q == 1) return fma(e.l20, G[0], fma(e.ku, G[1], (-e.k) * G[2]));
+        return fma(e.a3, G[0], fma(e.a4, G[1], e.D * G[2]));
     }
 }
 
@@ -534,12 +537,12 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
                     if (o == 0) {
                         const double f0 = w[q], fm1 = b[q], fm2 = a[q];
                         cc[q] = f0;
-                        isl[q] = fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2));
+                        isl[q] = fmax(fabs(f0 - fm1), fabs(fma(-2.0, fm1, f0) + fm2));
                     }
                     if (o == 1) a[q] = w[q];
                     if (o == 2) {
                         const double f0 = cc[q], fp1 = a[q], fp2 = w[q];
-                        is0[q] = fmin(isl[q], fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2)));
+                        is0[q] = fmin(isl[q], fmax(fabs(f0 - fp1), fabs(fma(-2.0, fp1, f0) + fp2)));
                     }
                 }
                 // Keep both chains advancing cell by cell: without this the
@@ -586,12 +589,12 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
                     if (o == 1) {
                         const double f0 = w[q], fp1 = b[q], fp2 = a[q];
                         cc[q] = f0;
-                        isr[q] = fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2));
+                        isr[q] = fmax(fabs(f0 - fp1), fabs(fma(-2.0, fp1, f0) + fp2));
                     }
                     if (o == 2) a[q] = w[q];
                     if (o == 3) {
                         const double f0 = cc[q], fm1 = a[q], fm2 = w[q];
-                        is0[q] = fmin(fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2)), isr[q]);
+                        is0[q] = fmin(fmax(fabs(f0 - fm1), fabs(fma(-2.0, fm1, f0) + fm2)), isr[q]);
                     }
                 }
                 // Keep both chains advancing cell by cell: without this the
