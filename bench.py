@@ -26,30 +26,28 @@ METRIC = "ENO-MR cell-updates/s per RK stage (FP64), % of roofline; adjoint/fwd 
 PEAK_FP64_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz
 
 
-def algorithmic_flops_per_face(order, nv=4):
-    """FP64 flops (FMA = 2) of one face on the smooth path, as the method needs them.
+# Algorithmic operation count of the 2D Euler operator (FP64 flops, fma = 2;
+# add/sub/mul/div/sqrt/min/max/compare = 1; structural zeros and ones of the
+# eigenvectors free).  The same rule is instrumented in the oracle
+# (orc_ops_begin/orc_ops_end), and tests/test_accounting.py checks that this
+# log-based count equals the oracle's instrumented count on the same data.
+ROE_OPS = 44            # Roe average and the entries of L and R in use
+PROJ_OPS = 20           # L G of one cell: u-c/u+c rows share 3, 4 + 4, u row 7, shear 2
+BACK_OPS = 24           # w-hat+ + w-hat- (4) and R w-hat (20)
+IS0_OPS = 11
+STAGE_OPS = 36          # per cell and sweep: primitives, LF split, sqrt(rho)
+DIFF_OPS = {"x": 8, "y": 12}               # -(dF)/h, and the add of L_x in the y sweep
+RK_OPS = {1: 8, 2: 20, 3: 20}              # per cell: the SSP-RK3 stage combination
 
-    Roe average and eigenvectors (41); projection of both split fluxes over the
-    two (2r-1)-cell windows (23 per cell and sign: three 4-term rows and the
-    2-term shear row); full-stencil IS and flux chains for every field and sign
-    (2 x (4r-3)); the baseline indicators IS0 and the comparison (12 per field
-    and sign); back-projection (28).
-    """
-    assert nv == 4
-    r = (order + 1) // 2
-    return 41 + 46 * (2 * r - 1) + 16 * (4 * r - 3) + 96 + 28
 
+def pair_ops_table(order):
+    """Ops of one (field, sign) reconstruction by its logged candidate C.
 
-def extra_flops_table(order):
-    """Extra flops of a (field, sign) reconstruction that chose candidate C >= 1.
-
-    The full stencil failed, so the indicators of the remaining candidates are
-    needed: one difference table of the (2r-1)-cell window gives all of them
-    ((2r-2)(2r-1)/2 - 1 subtractions, levels 1..2r-3), plus one compare per
-    candidate with m, n >= 1.  Then the chosen stencil's flux chain
-    (2 (m+n+1) - 1), or the minmod branch (6).  Log entries from the IS0 = 0
-    shortcut (about 0.5% of pairs on this workload) read as minmod and are
-    counted the same way.
+    C = 0: IS0, the full stencil's b_l chain and compare, its a_l chain.
+    C >= 1: IS0 and the failed full stencil, then the indicators of
+    candidates 1..C, the cheaper of the b_l chains scanned in list order and
+    one difference table of the window plus a compare per candidate tested;
+    then the chosen a_l chain, or minmod (7) when no candidate passes.
     """
     import paper_2311_15504_amd as enomr
     mn, _, _ = enomr.coefficients(order)
@@ -57,20 +55,30 @@ def extra_flops_table(order):
     r = (order + 1) // 2
     last_full = nc - 4                      # candidates with m, n >= 1 are 0..nc-4
     table = (2 * r - 2) * (2 * r - 1) // 2 - 1
+    chain = lambda c: 2 * (mn[c, 0] + mn[c, 1]) + 1
     tab = np.zeros(256)
+    tab[0] = IS0_OPS + chain(0) + 1 + chain(0)
     for C in range(1, nc):
-        e = table + last_full
-        if C <= last_full:
-            e += 2 * (mn[C, 0] + mn[C, 1] + 1) - 1
-        else:
-            e += 6
+        tested = min(C, last_full)
+        scan = sum(chain(c) + 1 for c in range(1, tested + 1))
+        e = IS0_OPS + chain(0) + 1 + min(scan, table + tested)
+        e += chain(C) if C <= last_full else 7
         tab[C] = e
     return tab
 
 
-def cell_flops(stage_out):
-    """Per-cell flops of a sweep: staging (36) plus the output (x: 8; y with RK: 32)."""
-    return 36 + stage_out
+def face_ops(order):
+    """Ops of one face besides its 8 reconstructions."""
+    r = (order + 1) // 2
+    return ROE_OPS + 2 * (2 * r - 1) * PROJ_OPS + BACK_OPS
+
+
+def sweep_ops(order, nfaces, ncells, hist, direction, rk_stage=None):
+    """Ops of one sweep: nfaces faces whose (field, sign) choices have the
+    histogram `hist` (counts per logged candidate), ncells cells."""
+    pair = pair_ops_table(order)
+    cell = STAGE_OPS + DIFF_OPS[direction] + (RK_OPS[rk_stage] if rk_stage else 0)
+    return nfaces * face_ops(order) + float((np.asarray(hist, dtype=np.float64) * pair).sum()) + ncells * cell
 
 
 def run(args):
@@ -137,11 +145,11 @@ def run(args):
             hist_x += torch.bincount(xs.long(), minlength=256).double()
             hist_y += torch.bincount(ys.long(), minlength=256).double()
     ctx.check()
-    extra = torch.from_numpy(extra_flops_table(order)).cuda()
     launches = 3 * args.steps
-    face_fl = algorithmic_flops_per_face(order)
-    fl_x = (n * n * face_fl + n * n * cell_flops(8)) * launches + float((hist_x * extra).sum())
-    fl_y = ((n + 1) * n * face_fl + n * n * cell_flops(32)) * launches + float((hist_y * extra).sum())
+    # x faces: n per periodic row (face n repeats face 0); y faces: n+1 per outflow column
+    fl_x = sweep_ops(order, n * n * launches, n * n * launches, hist_x.cpu().numpy(), "x")
+    fl_y = (sweep_ops(order, (n + 1) * n * launches, n * n * launches, hist_y.cpu().numpy(), "y")
+            + n * n * args.steps * (RK_OPS[1] + RK_OPS[2] + RK_OPS[3]))
     ms_x, nl_x = prof["sweep_x"]
     ms_y, nl_y = prof["sweep_y"]
     # dominant kernel: the sweep with the larger total time
@@ -173,7 +181,10 @@ def run(args):
                    "nx": n, "ny": n, "order": order, "cfl": cfl, "seed": args.seed},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": recorded_traffic(dom), "kernel": dom,
-                     "algorithmic_flop_per_launch": per_launch, "avg_launch_ms": avg_ms},
+                     "algorithmic_flop_per_launch": per_launch, "avg_launch_ms": avg_ms,
+                     "traffic_gbps": (recorded_traffic(dom) / (avg_ms * 1e-3) / 1e9
+                                      if recorded_traffic(dom) else None),
+                     "valu_lane_instr_per_flop": valu_ratio(dom, per_launch)},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
         "full_stencil_fraction": {"x": smooth_frac_x, "y": smooth_frac_y},
         "wall_s": wall,
@@ -306,9 +317,9 @@ def sweep_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when there is none or the sources changed since it was taken."""
+def recorded_counters():
+    """The committed counter record (HBM bytes and VALU instructions per
+    launch), or None when there is none or the sources changed since."""
     try:
         with open(TRAFFIC_MD) as fh:
             text = fh.read()
@@ -320,14 +331,29 @@ def recorded_traffic(kernel):
     rec = json.loads(m.group(1))
     if rec.get("source_sha256") != sweep_source_hash():
         return None
-    return rec.get("bytes_per_launch", {}).get(kernel)
+    return rec
 
 
-def traffic_summary(fetch_dir, write_dir, copy_mib, command):
+def valu_ratio(kernel, flop_per_launch):
+    """Executed VALU lane-instructions (64 per wave-instruction, masked lanes
+    included) per algorithmic flop: divergence and overhead against the
+    operation count (0.5 would be all-FMA code with nothing wasted)."""
+    rec = recorded_counters()
+    v = None if rec is None else rec.get("valu_wave_instr_per_launch", {}).get(kernel)
+    return None if v is None else v * 64.0 / flop_per_launch
+
+
+def recorded_traffic(kernel):
+    rec = recorded_counters()
+    return None if rec is None else rec.get("bytes_per_launch", {}).get(kernel)
+
+
+def traffic_summary(fetch_dir, write_dir, valu_dir, copy_mib, command):
     """Per-launch HBM bytes of the two sweeps from rocprofv3 FETCH_SIZE and
     WRITE_SIZE runs (KiB per dispatch, summed over the counter's instances),
     each scaled by what the same counter reads for torch's copy of copy_mib
-    MiB (the calibration copy of --calib-copy-mib)."""
+    MiB (the calibration copy of --calib-copy-mib); and their VALU
+    instructions per launch from an SQ_INSTS_VALU run."""
     import csv
     import glob
 
@@ -354,12 +380,14 @@ def traffic_summary(fetch_dir, write_dir, copy_mib, command):
 
     fe = per_dispatch(fetch_dir, "FETCH_SIZE")
     wr = per_dispatch(write_dir, "WRITE_SIZE")
+    vi = {k: v for k, v in per_dispatch(valu_dir, "SQ_INSTS_VALU").items() if k != "copy"}
     kib = copy_mib * 1024.0
     f_fetch, f_write = kib / fe["copy"], kib / wr["copy"]
     out = {}
     for k in ("k_euler_sweep (x faces)", "k_euler_sweep (y faces)"):
         out[k] = (fe[k] * f_fetch + wr[k] * f_write) * 1024.0
     rec = {"source_sha256": sweep_source_hash(), "bytes_per_launch": out,
+           "valu_wave_instr_per_launch": vi,
            "fetch_kib_per_dispatch": fe, "write_kib_per_dispatch": wr,
            "calibration": {"copy_mib": copy_mib, "fetch_scale": f_fetch, "write_scale": f_write}}
     lines = ["# HBM traffic: 2D Euler 2048x2048, ENO-MR order 17, sweep kernels", "",
@@ -374,6 +402,8 @@ def traffic_summary(fetch_dir, write_dir, copy_mib, command):
         b = out.get(k, (fe[k] * f_fetch + wr[k] * f_write) * 1024.0)
         lines.append("| %s | %.0f | %.0f | %.4g |" % (k, fe[k], wr[k], b))
     n2 = 2048 * 2048 * 4 * 8
+    lines += ["", "VALU wave-instructions per launch (SQ_INSTS_VALU, per wave of 64 lanes): x sweep %.4g, "
+              "y sweep %.4g." % (vi["k_euler_sweep (x faces)"], vi["k_euler_sweep (y faces)"])]
     lines += ["", "Scale factors: fetch %.4f, write %.4f." % (f_fetch, f_write), "",
               "Compulsory bytes per launch: x sweep %.4g (read U_s, write L_x); y sweep %.4g (read U_s, L_x," % (2 * n2, 4 * n2),
               "U^n, write the stage state; %.4g at the first stage, where U_s is U^n)." % (3 * n2), "",
@@ -421,13 +451,13 @@ def main():
                     help="skip the stencil-logged replay that counts algorithmic work (counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a float64 tensor of this many MiB (counter calibration)")
-    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
-                    help="write the traffic summary from two rocprofv3 counter runs to stdout and exit")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "VALU_DIR", "COPY_MIB"),
+                    help="write the counter summary from three rocprofv3 counter runs to stdout and exit")
     ap.add_argument("--traffic-command", default="", help="command text recorded in the summary")
     args = ap.parse_args()
     if args.traffic_summary:
-        fd, wd, mib = args.traffic_summary
-        print(traffic_summary(fd, wd, int(mib), args.traffic_command))
+        fd, wd, vd, mib = args.traffic_summary
+        print(traffic_summary(fd, wd, vd, int(mib), args.traffic_command))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

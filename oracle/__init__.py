@@ -70,6 +70,10 @@ def lib():
         L.orc_roe_eigen.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
         L.orc_euler1d_rhs.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_long,
                                       ctypes.c_double, _dp, _dp, _u8p, _dp]
+        L.orc_ops_begin.restype = None
+        L.orc_ops_begin.argtypes = []
+        L.orc_ops_end.restype = ctypes.c_double
+        L.orc_ops_end.argtypes = []
         L.orc_euler2d_rhs.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_long, ctypes.c_long, ctypes.c_double, ctypes.c_double,
                                       _dp, _dp, _u8p, _u8p, _dp, _dp]
@@ -268,6 +272,18 @@ def euler2d_rhs(order, U, hx, hy, gamma=1.4, bcx=PERIODIC, bcy=OUTFLOW, with_idx
     if with_idx:
         return out, ix.reshape(ny, nx + 1, 4, 2), iy.reshape(ny + 1, nx, 4, 2), ax, ay
     return out
+
+
+def euler2d_rhs_ops(order, U, hx, hy, gamma=1.4, bcx=PERIODIC, bcy=OUTFLOW):
+    """(L(U), ix, iy, ops): the operator with its stencil logs and the
+    algorithmic operation count of evaluating it (see the counter in
+    enomr_oracle.c)."""
+    lib().orc_ops_begin()
+    try:
+        out, ix, iy, _, _ = euler2d_rhs(order, U, hx, hy, gamma, bcx, bcy, with_idx=True)
+    finally:
+        ops = lib().orc_ops_end()
+    return out, ix, iy, ops
 
 
 def euler2d_rhs_cells(order, U, hx, hy, cells, gamma=1.4, bcx=PERIODIC, bcy=OUTFLOW):

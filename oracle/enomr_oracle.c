@@ -39,6 +39,30 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* ------------------------------------------------------------------------ */
+/* Operation counter                                                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Algorithmic operation count of the Euler operator, taken as the method's
+ * steps run (the early exit of Step 3.1 included): FP64 flops with fma = 2;
+ * add, sub, mul, div, sqrt, min, max and compare = 1; |x|, negation and
+ * products or sums with a structural 0 or 1 of the eigenvectors are free.
+ * A shared subexpression counts once (the last two terms of the u-c and u+c
+ * rows of L, E + p of a cell).  The indicators of the candidates after a
+ * failed full stencil count as the cheaper of two ways to obtain them up to
+ * the accepted candidate: one b_l chain per candidate scanned, or one
+ * difference table of the window ((2r-2)(2r-1)/2 - 1 subtractions) with one
+ * compare per candidate.  The wave speeds, alpha and dt (a separate step) and
+ * the RK stage combination are not part of the operator count.
+ */
+static double g_ops;
+static int g_counting;
+
+void orc_ops_begin(void) { g_ops = 0.0; g_counting = 1; }
+double orc_ops_end(void) { g_counting = 0; return g_ops; }
+#define OPS(n) do { if (g_counting) g_ops += (double)(n); } while (0)
+
 #define ORC_MAXC 29
 #define ORC_MAXW 17
 
@@ -139,6 +163,7 @@ static double recon_face(const orc_table *T, const double *f, long j, int sign, 
     double isl = fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2));
     double isr = fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2));
     double is0 = fmin(isl, isr);
+    OPS(11);   /* two sides of (sub, mul, sub, add, max), then min */
 
     /* Step 2: IS of every candidate, Eqs. (CurrentIS), (ISCoe): for the full
        stencil |sum b_l f_{j+l}|, for the others the undivided difference over
@@ -156,12 +181,25 @@ static double recon_face(const orc_table *T, const double *f, long j, int sign, 
     }
 
     /* Step 3.1: first candidate in list order with m, n >= 1 and IS < IS0. */
+    double scan = 0.0;     /* ops of the b_l chains of candidates 1.. scanned so far */
+    int tested = 0;        /* candidates 1.. tested so far */
+    const int r = T->r;
+    const double table = (double)((2 * r - 2) * (2 * r - 1) / 2 - 1);
     for (int k = 0; k < T->ncand; ++k) {
-        if (T->m[k] >= 1 && T->n[k] >= 1 && is[k] < is0) {
-            *idx = k;
-            return stencil_dot(T->a[k], T->m[k], T->n[k], f, c, s);
+        if (T->m[k] >= 1 && T->n[k] >= 1) {
+            const int d = T->m[k] + T->n[k];
+            if (k == 0) OPS(2 * d + 1 + 1);     /* b_l chain and compare */
+            else { scan += 2 * d + 1 + 1; ++tested; }
+            if (is[k] < is0) {
+                if (k > 0) OPS(scan < table + tested ? scan : table + tested);
+                OPS(2 * d + 1);                 /* a_l chain */
+                *idx = k;
+                return stencil_dot(T->a[k], T->m[k], T->n[k], f, c, s);
+            }
         }
     }
+    OPS(scan < table + tested ? scan : table + tested);
+    OPS(7);   /* minmod: two slopes, their product, compare, |.| compare, f0 + mm/2 */
 
     /* Step 3.2: minmod between S_j^{j+1} and S_{j-1}^j, else S_j^j. */
     double da = fp1 - f0;      /* slope towards the downwind neighbour */
@@ -438,6 +476,7 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
     double *wp = (double *)malloc(sizeof(double) * nn);
     double *wm = (double *)malloc(sizeof(double) * nn);
     int st = ORC_OK;
+    const int counting = g_counting;
     if (!U || !Gp || !Gm || !Q || !wp || !wm) { st = ORC_EINVAL; goto done; }
 
     /* Ghosted line, primitive quantities and the LF split G = (F +- alpha U)/2. */
@@ -450,13 +489,26 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
             Gp[i * nv + v] = 0.5 * (Q[i].F[v] + t);
             Gm[i * nv + v] = 0.5 * (Q[i].F[v] - t);
         }
+        /* once per cell of the line (ghosts are copies): 1/rho, velocities,
+           kinetic energy, p, E + p, H, fluxes, the split (5 per component) and
+           sqrt(rho) of the Roe average */
+        if (i >= g && i < g + n) OPS(nv == 4 ? 36 : 27);
     }
 
     for (long f = 0; f <= n; ++f) {
         long j = f - 1 + g;      /* left cell of the face in the ghosted line */
         double Lm[4][4], Rm[4][4];
+        /* a periodic line's face n is its face 0 again: counted once */
+        g_counting = counting && !(bc == ORC_PERIODIC && f == n);
         if ((st = roe_eigen(nv, gamma, &U[j * nv], &Q[j], &U[(j + 1) * nv], &Q[j + 1], Lm, Rm)))
             goto done;
+        /* Roe average and the entries of L and R used below (0.5 q^2 is shared
+           by c^2 and R) */
+        OPS(nv == 4 ? 44 : 36);
+        /* L G over each window (2r-1 cells per sign): rows u-c and u+c share
+           their last two terms (3), then 2 fma each; the u row 7 (5 in 1D); the
+           shear row one fma */
+        OPS(2 * (2 * T->r - 1) * (nv == 4 ? 20 : 14));
         double what[4];
         for (int k = 0; k < nv; ++k) {
             /* characteristic field k of the split fluxes over the face's window */
@@ -473,10 +525,12 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
                 idx[(f * nv + k) * 2 + 1] = (uint8_t)km;
             }
         }
-        /* back to conserved components: F-hat = R w-hat */
+        /* back to conserved components: F-hat = R w-hat (w-hat+ + w-hat- first) */
         for (int v = 0; v < nv; ++v) Fhat[f * nv + v] = row_dot(Rm[v], what, nv);
+        OPS(nv == 4 ? 4 + 20 : 3 + 12);
     }
 done:
+    g_counting = counting;
     free(U); free(Gp); free(Gm); free(Q); free(wp); free(wm);
     return st;
 }
@@ -536,6 +590,7 @@ int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx,
         for (int v = 0; v < 4; ++v)
             for (long x = 0; x < nx; ++x)
                 Lx[v * plane + y * nx + x] = -((Fh[(x + 1) * 4 + v] - Fh[x * 4 + v]) * ihx);
+        OPS(8 * nx);
     }
     /* y sweep on the permuted state, then combine */
     static const int perm[4] = {0, 2, 1, 3};
@@ -555,6 +610,7 @@ int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx,
                 double ly = -((Fh[(y + 1) * 4 + v] - Fh[y * 4 + v]) * ihy);
                 dUdt[cv * plane + y * nx + x] = Lx[cv * plane + y * nx + x] + ly;
             }
+        OPS(12 * ny);
     }
 done:
     free(line); free(Fh); free(idl); free(Lx);

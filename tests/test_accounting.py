@@ -1,0 +1,56 @@
+"""The benchmark's algorithmic operation count (bench.sweep_ops, applied to
+stencil logs) equals the oracle's instrumented count of the same operator
+evaluation (orc_ops_begin/orc_ops_end, counted as the method's steps run, the
+early exit included).  No GPU: both sides use the oracle's own logs."""
+import numpy as np
+import pytest
+
+import bench
+import oracle
+import workloads
+
+
+def _hist(idx, drop_last_face):
+    a = idx[:, :-1] if drop_last_face == "x" else idx
+    return np.bincount(a.reshape(-1).astype(np.int64), minlength=256)[:256]
+
+
+@pytest.mark.parametrize("order", [9, 17])
+@pytest.mark.parametrize("bcx,bcy", [(oracle.PERIODIC, oracle.OUTFLOW), (oracle.OUTFLOW, oracle.OUTFLOW),
+                                     (oracle.PERIODIC, oracle.PERIODIC)])
+def test_log_based_count_equals_instrumented_oracle(order, bcx, bcy):
+    nx, ny = 41, 30
+    (x, y, hx, hy), U = workloads.euler2d_quadrants_vortices(order, nx, ny)
+    _, ix, iy, ops = oracle.euler2d_rhs_ops(order, U, hx, hy, bcx=bcx, bcy=bcy)
+    # ix: [ny][nx+1][4][2]; iy: [ny+1][nx][4][2]; a periodic line's last face repeats its first
+    ixl = ix[:, :nx] if bcx == oracle.PERIODIC else ix
+    iyl = iy[:ny] if bcy == oracle.PERIODIC else iy
+    hx_ = np.bincount(ixl.reshape(-1).astype(np.int64), minlength=256)[:256]
+    hy_ = np.bincount(iyl.reshape(-1).astype(np.int64), minlength=256)[:256]
+    fx = ny * (nx if bcx == oracle.PERIODIC else nx + 1)
+    fy = nx * (ny if bcy == oracle.PERIODIC else ny + 1)
+    got = bench.sweep_ops(order, fx, nx * ny, hx_, "x") + bench.sweep_ops(order, fy, nx * ny, hy_, "y")
+    assert hx_[1:].sum() > 0 and hy_[1:].sum() > 0      # the data exercises the fallback
+    assert got == ops, (got, ops)
+
+
+def test_smooth_face_count_closed_form():
+    # On smooth data every reconstruction takes the full stencil (C = 0): the
+    # count per face is the Roe/projection/back-projection part plus 8 times
+    # (IS0 + two (4r-3)-term chains + compare), per cell staging and difference.
+    order, n = 17, 128
+    r = (order + 1) // 2
+    x = np.linspace(-1.0, 1.0, n, endpoint=False)
+    X, Y = np.meshgrid(x, x)
+    rho = 1.0 + 0.2 * np.sin(np.pi * X) * np.cos(np.pi * Y)
+    u = 0.3 * np.sin(np.pi * (X + Y))
+    v = 0.2 * np.cos(np.pi * X) + 0.1 * np.sin(np.pi * Y)
+    p = 1.0 + 0.1 * np.sin(np.pi * Y) * np.cos(np.pi * X)
+    U = np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+    _, ix, iy, ops = oracle.euler2d_rhs_ops(order, U, 2.0 / n, 2.0 / n, bcx=oracle.PERIODIC,
+                                           bcy=oracle.PERIODIC)
+    assert not ix.any() and not iy.any()
+    ny, nx = rho.shape
+    per_face = 44 + 2 * (2 * r - 1) * 20 + 24 + 8 * (11 + 2 * (2 * (2 * r - 2) + 1) + 1)
+    expect = (ny * nx + nx * ny) * per_face + nx * ny * (36 + 8) + nx * ny * (36 + 12)
+    assert ops == expect
