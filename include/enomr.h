@@ -166,6 +166,21 @@ enomr_status enomr_profile_start(enomr_ctx *ctx);
 enomr_status enomr_profile_stop(enomr_ctx *ctx, double *ms, int64_t *launches);
 
 /*
+ * Linear SSP-RK(m, m-1) (Sec. 2.3, Eq. lSSPRK, coefficients Eq. lSSPRK_Coe,
+ * read as alpha_{m,m-1} = (2/m) alpha_{m-1,m-2}) for scalar 1D problems
+ * (ENOMR_ADVECTION, ENOMR_BURGERS), the time stepping of the paper's linear
+ * convergence tests (Sec. 4.1):
+ *   u^(0) = u^n,  u^(s) = u^(s-1) + dt/2 L(u^(s-1)),  s = 1..m-1,
+ *   u^{n+1} = sum_{k<m-1} alpha_{m,k} u^(k) + alpha_{m,m-1} (u^(m-1) + dt/2 L(u^(m-1))).
+ * The coefficients are computed in exact rational arithmetic and rounded to
+ * the nearest doubles.  U: device [nx]; dt is fixed; 2 <= m <= 18.
+ * ws: device workspace of enomr_lssp_workspace_size(prob, m) bytes.
+ */
+enomr_status enomr_lssp_workspace_size(const enomr_problem *prob, int m, size_t *bytes);
+enomr_status enomr_lssp_advance(enomr_ctx *ctx, const enomr_problem *prob, double *U, double dt, int64_t nsteps,
+                                int m, void *ws);
+
+/*
  * Frozen-stencil discrete adjoint (1D Euler problems).
  *
  * With the stencil choices, the per-stage alpha and the step size fixed from a

@@ -95,6 +95,8 @@ def lib():
             "enomr_check": ([_vp], st),
             "enomr_profile_start": ([_vp], st),
             "enomr_profile_stop": ([_vp, _vp, _vp], st),
+            "enomr_lssp_workspace_size": ([P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], st),
+            "enomr_lssp_advance": ([_vp, P, _vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int, _vp], st),
             "enomr_rhs_adjoint": ([_vp, P, _vp, _vp, _vp, _vp, _vp, _vp], st),
             "enomr_record_steps": ([_vp, P, _vp, ctypes.c_double, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp], st),
             "enomr_adjoint_steps": ([_vp, P, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp], st),
@@ -224,6 +226,17 @@ class Context:
     def check(self):
         self._sync_stream()
         _call("enomr_check", self.handle)
+
+    def lssp_advance(self, prob, U, dt, nsteps, m):
+        """nsteps linear SSP-RK(m, m-1) steps of a scalar line with fixed dt, in place."""
+        self._check_state(prob, U)
+        n = ctypes.c_size_t()
+        _call("enomr_lssp_workspace_size", ctypes.byref(prob), m, ctypes.byref(n))
+        ws = self.torch.empty(n.value, dtype=self.torch.uint8, device=self.device)
+        self._sync_stream()
+        _call("enomr_lssp_advance", self.handle, ctypes.byref(prob), _ptr(U), dt, nsteps, m, _ptr(ws))
+        self._sync_stream()
+        self.torch.cuda.current_stream(self.device).synchronize()   # ws is freed on return
 
     # -- frozen-stencil adjoint (1D Euler) ------------------------------------
 

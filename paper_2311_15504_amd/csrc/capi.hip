@@ -167,6 +167,7 @@ void timed(enomr_ctx* ctx, int cls, F&& launch)
 
 // Tile shapes (faces per line x lines per block).
 constexpr int kTF1 = 64;                  // 1D lines
+constexpr int kMaxLsspStages = 18;        // linear SSP-RK(m, m-1): m up to order 17 + 1
 constexpr int kTFx = 64, kTLx = 4;        // 2D x sweep
 constexpr int kTFy = 64, kTLy = 4;        // 2D y sweep
 
@@ -610,6 +611,120 @@ enomr_status enomr_advance(enomr_ctx* ctx, const enomr_problem* prob, double* U,
         if (enomr_status st = launch_alpha(ctx, *prob, U, ws, act)) return st;
         if (enomr_status st = launch_dt(ctx, *prob, cfl, ws, dt, t_end, dt_log, (long)s)) return st;
         if (enomr_status st = rk3_step(ctx, *prob, U, dt, ws, nullptr, act, true)) return st;
+    }
+    return ENOMR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Linear SSP-RK(m, m-1) (Sec. 2.3, Eqs. lSSPRK, lSSPRK_Coe) for scalar lines
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// alpha_{m,0..m-1} in exact rationals, rounded to the nearest doubles:
+// alpha_{2,0} = 0, alpha_{2,1} = 1; alpha_{m,k} = (2/k) alpha_{m-1,k-1} for
+// 1 <= k <= m-2; alpha_{m,m-1} = (2/m) alpha_{m-1,m-2};
+// alpha_{m,0} = 1 - sum_{k>=1} alpha_{m,k}.
+bool lssp_coefficients(int m, double* out)
+{
+    typedef __int128 i128;
+    struct Q { i128 p, q; };
+    auto gcd = [](i128 a, i128 b) {
+        if (a < 0) a = -a;
+        while (b != 0) { i128 t = a % b; a = b; b = t; }
+        return a;
+    };
+    auto make = [&](i128 p, i128 q) {
+        i128 g = gcd(p, q);
+        if (g == 0) g = 1;
+        return Q{p / g, q / g};
+    };
+    std::vector<Q> a = {Q{0, 1}, Q{1, 1}};
+    for (int mm = 3; mm <= m; ++mm) {
+        std::vector<Q> c(mm, Q{0, 1});
+        for (int k = 1; k <= mm - 2; ++k) c[k] = make(2 * a[k - 1].p, k * a[k - 1].q);
+        c[mm - 1] = make(2 * a[mm - 2].p, mm * a[mm - 2].q);
+        Q sum{0, 1};
+        for (int k = 1; k < mm; ++k) sum = make(sum.p * c[k].q + c[k].p * sum.q, sum.q * c[k].q);
+        c[0] = make(sum.q - sum.p, sum.q);
+        a = c;
+    }
+    const i128 lim = ((i128)1) << 53;
+    for (int k = 0; k < m; ++k) {
+        i128 p = a[k].p < 0 ? -a[k].p : a[k].p;
+        if (p >= lim || a[k].q >= lim) return false;
+        out[k] = (double)(long long)a[k].p / (double)(long long)a[k].q;
+    }
+    return true;
+}
+
+enomr_status check_lssp(const enomr_problem* prob, int m)
+{
+    if (enomr_status st = check_problem(prob)) return st;
+    if (prob->ndim != 1 || prob->system == ENOMR_EULER)
+        return fail(ENOMR_EINVAL, "linear SSP-RK is provided for scalar 1D problems");
+    if (m < 2 || m > kMaxLsspStages) return fail(ENOMR_EINVAL, "m must be in 2..18");
+    return ENOMR_OK;
+}
+
+// The problem's workspace, then m stage states, L, and device scalars.
+size_t lssp_stage_offset(const enomr_problem& p) { return align_up(layout(p).total); }
+
+}  // namespace
+
+enomr_status enomr_lssp_workspace_size(const enomr_problem* prob, int m, size_t* bytes)
+{
+    if (enomr_status st = check_lssp(prob, m)) return st;
+    if (!bytes) return fail(ENOMR_EINVAL, "bytes is NULL");
+    const size_t line = align_up(sizeof(double) * (size_t)prob->nx);
+    *bytes = lssp_stage_offset(*prob) + (size_t)(m + 1) * line + 256 + align_up(sizeof(double) * kMaxLsspStages);
+    return ENOMR_OK;
+}
+
+enomr_status enomr_lssp_advance(enomr_ctx* ctx, const enomr_problem* prob, double* U, double dt, int64_t nsteps,
+                                int m, void* ws)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    if (enomr_status st = check_lssp(prob, m)) return st;
+    if (!U || !ws) return fail(ENOMR_EINVAL, "NULL array");
+    if (!(dt > 0.0) || nsteps < 0) return fail(ENOMR_EINVAL, "bad dt or nsteps");
+    double coef[kMaxLsspStages];
+    if (!lssp_coefficients(m, coef)) return fail(ENOMR_EINVAL, "coefficients not representable");
+    const enomr_problem& p = *prob;
+    const long n = p.nx;
+    const size_t line = align_up(sizeof(double) * (size_t)n);
+    char* base = static_cast<char*>(ws) + lssp_stage_offset(p);
+    // stage k at base + k * line; then L, hdt and the coefficients
+    double* L = reinterpret_cast<double*>(base + (size_t)m * line);
+    double* hdt = reinterpret_cast<double*>(base + (size_t)(m + 1) * line);
+    double* dcoef = reinterpret_cast<double*>(base + (size_t)(m + 1) * line + 256);
+    HIP_TRY(hipMemcpyAsync(dcoef, coef, sizeof(double) * m, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, ctx->stream, hdt, 1L, 0.5 * dt);
+    HIP_TRY(hipGetLastError());
+    auto stage = [&](int k) { return reinterpret_cast<double*>(base + (size_t)k * line); };
+    for (int64_t step = 0; step < nsteps; ++step) {
+        HIP_TRY(hipMemcpyAsync(stage(0), U, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
+        for (int s = 1; s < m; ++s) {
+            if (enomr_status st = launch_alpha(ctx, p, stage(s - 1), ws, nullptr)) return st;
+            StageOut so;
+            so.Un = stage(s - 1);
+            so.Lprev = nullptr;
+            so.out = stage(s);
+            so.dt = hdt;
+            so.stage = 1;   // u^(s) = u^(s-1) + hdt L(u^(s-1))
+            if (enomr_status st = launch_operator(ctx, p, stage(s - 1), so, nullptr, ws, nullptr)) return st;
+        }
+        if (enomr_status st = launch_alpha(ctx, p, stage(m - 1), ws, nullptr)) return st;
+        StageOut so;
+        so.Un = nullptr;
+        so.Lprev = nullptr;
+        so.out = L;
+        so.dt = nullptr;
+        so.stage = 0;
+        if (enomr_status st = launch_operator(ctx, p, stage(m - 1), so, nullptr, ws, nullptr)) return st;
+        hipLaunchKernelGGL(k_lssp_combine, dim3(blocks_for(n, 256)), dim3(256), 0, ctx->stream, stage(0),
+                           (long)(line / sizeof(double)), n, m, dcoef, L, hdt, U);
+        HIP_TRY(hipGetLastError());
     }
     return ENOMR_OK;
 }

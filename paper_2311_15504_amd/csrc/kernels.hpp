@@ -267,6 +267,21 @@ __global__ __launch_bounds__(TF) void k_scalar_sweep(const double* __restrict__ 
     }
 }
 
+// Last stage of the linear SSP-RK(m, m-1) step (Sec. 2.3, Eq. lSSPRK):
+// u = sum_{k < m-1} a_k u^(k) + a_{m-1} (u^(m-1) + hdt L), the sum taken in
+// ascending k from zero, each term a product then an add.
+// Stage k starts at stages + k * stride.
+__global__ void k_lssp_combine(const double* __restrict__ stages, long stride, long n, int m,
+                               const double* __restrict__ coef, const double* __restrict__ L,
+                               const double* __restrict__ hdt, double* __restrict__ u)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < m - 1; ++k) acc = acc + coef[k] * stages[k * stride + i];
+    u[i] = acc + coef[m - 1] * (stages[(m - 1) * stride + i] + *hdt * L[i]);
+}
+
 // ---------------------------------------------------------------------------
 // Euler: Roe-averaged eigenvectors at a face (Sec. 4 preamble) and the
 // characteristic sweep.

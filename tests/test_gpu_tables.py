@@ -1,0 +1,102 @@
+"""The paper's printed convergence rows reproduced on the GPU: linear
+SSP-RK(m, m-1) with the scalar advection operator (Sec. 4.1, Tables
+1DAdvectionConvergence*) and SSP-RK3 with Burgers (Sec. 4.2, Table
+1DBurgersConvergence), each run bitwise equal to the oracle's run."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from test_oracle_pins import ADVECTION_CASES, BURGERS_DT, _burgers_exact, _errors, _golden_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_15504_amd as enomr
+    c = enomr.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("order,n,m,steps", [(5, 50, 2, 7), (9, 77, 6, 5), (13, 130, 14, 3), (17, 45, 18, 4)])
+def test_lssp_matches_oracle_bitwise(ctx, order, n, m, steps):
+    import paper_2311_15504_amd as enomr
+    _, h, u0 = workloads.advection_sines_step(order + m, n)
+    ref = oracle.scalar_lssp_run(order, u0, h, 0.4 * h, steps, m)
+    prob = enomr.Problem.scalar(enomr.ADVECTION, n, h, order)
+    U = _dev(u0[None])
+    ctx.lssp_advance(prob, U, 0.4 * h, steps, m)
+    ctx.check()
+    assert np.array_equal(U.cpu().numpy()[0], ref)
+
+
+def test_lssp_rejects_bad_arguments(ctx):
+    import paper_2311_15504_amd as enomr
+    _, h, u0 = workloads.advection_sines_step(1, 40)
+    prob = enomr.Problem.scalar(enomr.ADVECTION, 40, h, 5)
+    for m in (1, 19):
+        with pytest.raises(enomr.EnomrError):
+            ctx.lssp_advance(prob, _dev(u0[None]), h, 1, m)
+    (x, y, hx, hy), U2 = workloads.euler2d_quadrants_vortices(0, 32, 32)
+    with pytest.raises(enomr.EnomrError):
+        ctx.lssp_advance(enomr.Problem.euler2d(32, 32, hx, hy, 5), _dev(U2), hx, 1, 4)
+
+
+@pytest.mark.parametrize("order,alpha,h", ADVECTION_CASES)
+def test_advection_rows_on_gpu(ctx, order, alpha, h):
+    import paper_2311_15504_amd as enomr
+    rows = {(o, lam, a, hh): (l1, li) for (o, lam, a, hh, l1, li) in _golden_rows("advection")}
+    n = int(2 / h)
+    for lam in (1.0, 1e6):
+        x, hh, u0 = workloads.sin_power(alpha, lam, n)
+        prob = enomr.Problem.scalar(enomr.ADVECTION, n, hh, order)
+        U = _dev(u0[None])
+        # linear SSP-RK(m, m-1) with m - 1 = order and dt = h (Sec. 4 preamble), t = 2
+        ctx.lssp_advance(prob, U, hh, n, order + 1)
+        ctx.check()
+        u = U.cpu().numpy()[0]
+        assert np.array_equal(u, oracle.scalar_lssp_run(order, u0, hh, hh, n, order + 1))
+        l1, linf = _errors(u, u0)
+        p1, pinf = rows[(order, lam, alpha, h)]
+        assert float("%.2e" % l1) == pytest.approx(p1, rel=1e-9), (l1, p1)
+        assert float("%.2e" % linf) == pytest.approx(pinf, rel=1e-9), (linf, pinf)
+
+
+@pytest.mark.parametrize("order", [5, 9, 13, 17])
+def test_burgers_rows_on_gpu(ctx, order):
+    import torch
+    import paper_2311_15504_amd as enomr
+    from fractions import Fraction
+    lam = 1.0
+    h = Fraction(1, 128) if order == 5 else Fraction(1, 64)
+    rows = {(o, la, hh): (l1, li) for (o, la, _, hh, l1, li) in _golden_rows("burgers")}
+    p1, pinf = rows[(order, lam, h)]
+    n = int(2 / h)
+    x, hh, u0 = workloads.burgers_sin3(lam, n)
+    C, e = BURGERS_DT[order]
+    dt = C * hh ** float(e) / lam
+    T = 0.1 / lam
+    prob = enomr.Problem.scalar(enomr.BURGERS, n, hh, order, split=enomr.SPLIT_NONE)
+    U = _dev(u0[None])
+    t = 0.0
+    while t < T:                          # fixed dt, the last step cut to end at T
+        step = dt if t + dt <= T else T - t
+        ctx.ssprk3_step(prob, U, torch.tensor([step], dtype=torch.float64, device="cuda"))
+        t += step
+    ctx.check()
+    u = U.cpu().numpy()[0]
+    ref = oracle.scalar_ssprk3_run(order, u0, hh, dt, t_end=T, flux=oracle.BURGERS, split=oracle.SPLIT_NONE)
+    assert np.array_equal(u, ref)
+    l1, linf = _errors(u, _burgers_exact(x, T, lam))
+    assert l1 == pytest.approx(p1, rel=0.025)
+    assert linf == pytest.approx(pinf, rel=0.025)
