@@ -254,6 +254,65 @@ def run_batched(args):
             "speedup_vs_per_problem": value / value_pp, "sample_bitwise_equal": bool(same)}
 
 
+def run_batched_2d(args):
+    """Batched 2D workload: independent 2D Euler problems, nx, ny ~ U{32..192},
+    orders {7, 9, 13, 17}, seeded quadrants + vortices, x periodic / y outflow,
+    `batch_steps` SSP-RK3 steps in one graph launch of the persistent 2D kernel,
+    against per-problem launches of a sample of the same problems."""
+    import torch
+
+    import paper_2311_15504_amd as enomr
+    import workloads
+
+    cfl = 0.5
+    steps = args.batch2d_steps
+    plist = workloads.batched_problems_2d(args.seed, nprob=args.batch2d_problems)
+    probs = [enomr.Problem.euler2d(p["nx"], p["ny"], p["hx"], p["hy"], p["order"]) for p in plist]
+    host = [p["U"] for p in plist]
+    states = [torch.from_numpy(U).cuda() for U in host]
+    ctx = enomr.Context(0)
+    batch = enomr.Batch(ctx, probs, states, autotune=False)
+    info = batch.info()
+    batch.advance(cfl, 1)                           # warm-up step
+    ctx.check()
+    for U, U0 in zip(states, host):
+        U.copy_(torch.from_numpy(U0))
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    batch.advance(cfl, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.check()
+    ms = e0.elapsed_time(e1)
+    cells = sum(p["nx"] * p["ny"] for p in plist)
+    value = cells * 3 * steps / (ms * 1e-3)
+    rng = np.random.default_rng(args.seed + 11)
+    sample = rng.choice(len(plist), size=min(args.batch_sample, len(plist)), replace=False)
+    Us = [torch.from_numpy(host[i]).cuda() for i in sample]
+    ctx.advance(probs[sample[0]], Us[0].clone(), cfl, 1)
+    torch.cuda.synchronize()
+    e0.record()
+    for k, i in enumerate(sample):
+        ctx.advance(probs[i], Us[k], cfl, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.check()
+    ms_pp = e0.elapsed_time(e1)
+    cells_pp = sum(plist[i]["nx"] * plist[i]["ny"] for i in sample)
+    value_pp = cells_pp * 3 * steps / (ms_pp * 1e-3)
+    same = all(torch.equal(states[i], Us[k]) for k, i in enumerate(sample))
+    batch.close()
+    ctx.close()
+    return {"workload": "%d independent 2D Euler problems, nx, ny ~ U{32..192}, orders {7,9,13,17}, seeded "
+                        "quadrants + vortices, %d SSP-RK3 steps at CFL 0.5, one graph launch" % (len(plist), steps),
+            "value": value, "unit": "cell-updates/s", "ms": ms, "total_cells": cells,
+            "workgroups": info["workgroups"],
+            "per_problem_launches": {"value": value_pp, "sample_problems": int(len(sample)), "ms": ms_pp},
+            "speedup_vs_per_problem": value / value_pp, "sample_bitwise_equal": bool(same)}
+
+
 def run_adjoint(args):
     """Adjoint workload: 1D Euler, N = 8192, order 9, smooth periodic data, 400
     SSP-RK3 steps checkpointed every 20; loss = h sum (rho_T - rho*)^2.
@@ -435,16 +494,20 @@ def cpu_baseline(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--order", type=int, default=17)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-order13", action="store_true", help="skip the order-13 run of the same workload")
     ap.add_argument("--batch-problems", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-sample", type=int, default=64)
+    ap.add_argument("--no-batched-2d", action="store_true")
+    ap.add_argument("--batch2d-problems", type=int, default=256)
+    ap.add_argument("--batch2d-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--no-replay", action="store_true",
@@ -465,7 +528,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     out = run(args)
+    if not args.no_order13 and args.order == 17:
+        import copy
+        a13 = copy.copy(args)
+        a13.order = 13
+        o13 = run(a13)
+        out["order13"] = {k: o13[k] for k in ("value", "unit", "ms_per_step", "kernels_ms_per_step")}
+        out["order13"]["roofline_frac"] = o13["roofline"]["frac"] if o13.get("roofline") else None
     out["batched"] = None if args.no_batched else run_batched(args)
+    out["batched_2d"] = None if (args.no_batched or args.no_batched_2d) else run_batched_2d(args)
     out["adjoint"] = None if args.no_adjoint else run_adjoint(args)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args)
     if args.calib_copy_mib:

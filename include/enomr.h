@@ -211,22 +211,27 @@ enomr_status enomr_adjoint_steps(enomr_ctx *ctx, const enomr_problem *prob, int6
                                  void *ws);
 
 /*
- * Batched persistent execution: many independent 1D Euler problems (uneven
- * lengths and orders) advanced together by one persistent launch replayed
- * from a hipGraph.  Each problem advances with its own per-stage alpha and
+ * Batched persistent execution: many independent 1D and 2D Euler problems
+ * (uneven sizes and orders) advanced together by persistent launches replayed
+ * from one hipGraph.  Each problem advances with its own per-stage alphas and
  * CFL time step exactly as enomr_advance() would advance it alone, and its
- * result is bitwise equal to that run.
+ * result is bitwise equal to that run.  A workgroup takes a whole problem
+ * from a work queue (longest first) and runs all its steps; the 1D and the 2D
+ * problems have a kernel each, the two running side by side in the graph.
  *
- * enomr_batch_create: probs[nprob] (ndim 1, ENOMR_EULER, any order 5..17),
- * U[nprob] device pointers to the problems' [3][nx] states, bound to the batch
- * for its lifetime and advanced in place.  The batch allocates its own stage
- * workspace (2 states per problem).  autotune = 1 times one step of the
- * whole batch on scratch copies for each tile width (64, 128, 256 faces) and
+ * enomr_batch_create: probs[nprob] (ENOMR_EULER, ndim 1 or 2, any order
+ * 5..17), U[nprob] device pointers to the problems' states ([3][nx] or
+ * [4][ny][nx]), bound to the batch for its lifetime and advanced in place.
+ * The batch allocates its own workspace (2 stage states per problem; for 2D
+ * also L_x and the per-line alphas).  autotune = 1 times one step of the 1D
+ * problems on scratch copies for each tile width (64, 128, 256 faces) and
  * keeps the fastest; 0 uses 128; 64, 128 or 256 use that width; any other
- * value is ENOMR_EINVAL.  The work queue hands out problems longest first.
+ * value is ENOMR_EINVAL.  2D problems use the 64 x 4 tiles of the
+ * single-problem kernels.
  * enomr_batch_advance: nsteps SSP-RK3 steps of every problem at CFL `cfl`.
- * enomr_batch_info: chosen tile width, workgroups, and the autotune times (ms,
- * for widths 64/128/256; zeros without autotune).  Any pointer may be NULL.
+ * enomr_batch_info: the 1D kernel's tile width, the workgroups of both
+ * kernels, and the autotune times (ms, for widths 64/128/256; zeros without
+ * autotune).  Any pointer may be NULL.
  */
 typedef struct enomr_batch enomr_batch;
 enomr_status enomr_batch_create(enomr_ctx *ctx, int32_t nprob, const enomr_problem *probs, double *const *U,

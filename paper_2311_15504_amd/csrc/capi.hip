@@ -35,15 +35,21 @@ struct enomr_ctx {
 
 struct enomr_batch {
     enomr_ctx* ctx = nullptr;
-    int nprob = 0;
-    int tf = 128;                  // faces per tile (autotuned)
-    unsigned nblocks = 0;          // persistent workgroups
+    int nprob = 0;                 // 1D problems
+    int nprob2 = 0;                // 2D problems
+    int tf = 128;                  // faces per tile of the 1D kernel (autotuned)
+    unsigned nblocks = 0;          // persistent workgroups of the 1D kernel
+    unsigned nblocks2 = 0;         // persistent workgroups of the 2D kernel
     BatchProb* d_probs = nullptr;
     int* d_order = nullptr;
-    int* d_queue = nullptr;
+    BatchProb2* d_probs2 = nullptr;
+    int* d_order2 = nullptr;
+    int* d_queue = nullptr;        // [2]: the 1D and the 2D kernel's work counters
     BatchParams* d_params = nullptr;
-    double* d_ws = nullptr;        // stage states of every problem
+    double* d_ws = nullptr;        // stage states (and 2D line buffers) of every problem
     hipStream_t cap = nullptr;     // capture stream
+    hipStream_t cap2 = nullptr;    // second capture stream (2D kernel beside the 1D one)
+    hipEvent_t fork = nullptr, join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double tune_ms[3] = {0, 0, 0}; // one-step times of the tile widths 64, 128, 256
@@ -841,6 +847,20 @@ hipError_t launch_batch(enomr_batch* b, int tf, const BatchProb* probs, hipStrea
     return hipGetLastError();
 }
 
+unsigned batch_blocks2(int nprob)
+{
+    int per_cu = 0, ncu = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_euler2d, kB2TF * kB2TL, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    if (ncu < 1) ncu = 1;
+    long nb = (long)per_cu * ncu;
+    if (nb > nprob) nb = nprob;
+    return (unsigned)(nb < 1 ? 1 : nb);
+}
+
 unsigned batch_blocks(int tf, int nprob)
 {
     int per_cu = 0, ncu = 0, dev = 0;
@@ -862,8 +882,13 @@ void batch_free(enomr_batch* b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->cap2) (void)hipStreamDestroy(b->cap2);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
     (void)hipFree(b->d_probs);
     (void)hipFree(b->d_order);
+    (void)hipFree(b->d_probs2);
+    (void)hipFree(b->d_order2);
     (void)hipFree(b->d_queue);
     (void)hipFree(b->d_params);
     (void)hipFree(b->d_ws);
@@ -880,82 +905,135 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
     if (autotune != 0 && autotune != 1 && autotune != 64 && autotune != 128 && autotune != 256)
         return fail(ENOMR_EINVAL, "autotune must be 0, 1, 64, 128 or 256");
     *out = nullptr;
-    std::vector<BatchProb> hp(nprob);
-    std::vector<double> cost(nprob);
+    // 1D problems (index list i1) and 2D problems (i2), each with its stage workspace
+    std::vector<int> i1, i2;
     size_t total = 0;
     for (int i = 0; i < nprob; ++i) {
         const enomr_problem& p = probs[i];
         if (enomr_status st = check_problem(&p)) return st;
-        if (p.system != ENOMR_EULER || p.ndim != 1)
-            return fail(ENOMR_EINVAL, "batched problems must be 1D Euler");
+        if (p.system != ENOMR_EULER) return fail(ENOMR_EINVAL, "batched problems must be Euler problems");
         if (!U[i]) return fail(ENOMR_EINVAL, "NULL state in batch");
-        total += align_up(sizeof(double) * 3 * (size_t)p.nx) * 2;
+        if (p.ndim == 1) {
+            i1.push_back(i);
+            total += align_up(sizeof(double) * 3 * (size_t)p.nx) * 2;
+        } else {
+            i2.push_back(i);
+            const size_t plane = sizeof(double) * (size_t)p.nx * (size_t)p.ny;
+            total += align_up(4 * plane) * 3 + align_up(sizeof(double) * (size_t)p.ny) +
+                     align_up(sizeof(double) * (size_t)p.nx);
+        }
     }
     enomr_batch* b = new enomr_batch;
     b->ctx = ctx;
-    b->nprob = nprob;
+    b->nprob = (int)i1.size();
+    b->nprob2 = (int)i2.size();
     auto bail = [&](enomr_status st, const std::string& m) {
         batch_free(b);
         return fail(st, m);
     };
     if (hipMalloc(&b->d_ws, total) != hipSuccess) return bail(ENOMR_ENOMEM, "cannot allocate batch workspace");
+    char* wsb = reinterpret_cast<char*>(b->d_ws);
     size_t off = 0;
-    for (int i = 0; i < nprob; ++i) {
-        const enomr_problem& p = probs[i];
-        const size_t sz = align_up(sizeof(double) * 3 * (size_t)p.nx);
-        BatchProb& q = hp[i];
-        q.U = U[i];
-        q.U1 = reinterpret_cast<double*>(reinterpret_cast<char*>(b->d_ws) + off);
-        q.U2 = reinterpret_cast<double*>(reinterpret_cast<char*>(b->d_ws) + off + sz);
-        off += 2 * sz;
+    auto take = [&](size_t bytes) {
+        double* p = reinterpret_cast<double*>(wsb + off);
+        off += align_up(bytes);
+        return p;
+    };
+    std::vector<BatchProb> hp(b->nprob);
+    std::vector<double> cost(b->nprob);
+    for (int k = 0; k < b->nprob; ++k) {
+        const enomr_problem& p = probs[i1[k]];
+        BatchProb& q = hp[k];
+        q.U = U[i1[k]];
+        q.U1 = take(sizeof(double) * 3 * (size_t)p.nx);
+        q.U2 = take(sizeof(double) * 3 * (size_t)p.nx);
         q.n = p.nx;
         q.ih = 1.0 / p.hx;
         q.gamma = p.gamma;
         q.R = (p.order + 1) / 2;
         q.bc = p.bc_x;
-        cost[i] = (double)p.nx * (double)(q.R + 3);
+        cost[k] = (double)p.nx * (double)(q.R + 3);
     }
-    // longest first: the work queue then hands out problems in LPT order
-    std::vector<int> order(nprob);
-    for (int i = 0; i < nprob; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
-    if (hipMalloc(&b->d_probs, sizeof(BatchProb) * nprob) != hipSuccess ||
-        hipMalloc(&b->d_order, sizeof(int) * nprob) != hipSuccess || hipMalloc(&b->d_queue, sizeof(int)) != hipSuccess ||
-        hipMalloc(&b->d_params, sizeof(BatchParams)) != hipSuccess)
+    std::vector<BatchProb2> hp2(b->nprob2);
+    std::vector<double> cost2(b->nprob2);
+    for (int k = 0; k < b->nprob2; ++k) {
+        const enomr_problem& p = probs[i2[k]];
+        const size_t plane = sizeof(double) * (size_t)p.nx * (size_t)p.ny;
+        BatchProb2& q = hp2[k];
+        q.U = U[i2[k]];
+        q.U1 = take(4 * plane);
+        q.U2 = take(4 * plane);
+        q.L = take(4 * plane);
+        q.ax = take(sizeof(double) * (size_t)p.ny);
+        q.ay = take(sizeof(double) * (size_t)p.nx);
+        q.nx = p.nx;
+        q.ny = p.ny;
+        q.ihx = 1.0 / p.hx;
+        q.ihy = 1.0 / p.hy;
+        q.gamma = p.gamma;
+        q.R = (p.order + 1) / 2;
+        q.bcx = p.bc_x;
+        q.bcy = p.bc_y;
+        cost2[k] = 2.0 * (double)p.nx * (double)p.ny * (double)(q.R + 3);
+    }
+    // longest first: the work queues then hand out problems in LPT order
+    auto lpt = [](const std::vector<double>& c) {
+        std::vector<int> o(c.size());
+        for (size_t i = 0; i < c.size(); ++i) o[i] = (int)i;
+        std::stable_sort(o.begin(), o.end(), [&](int a, int d) { return c[a] > c[d]; });
+        return o;
+    };
+    const std::vector<int> order = lpt(cost), order2 = lpt(cost2);
+    if (hipMalloc(&b->d_queue, sizeof(int) * 2) != hipSuccess || hipMalloc(&b->d_params, sizeof(BatchParams)) != hipSuccess)
         return bail(ENOMR_ENOMEM, "cannot allocate batch descriptors");
-    if (hipMemcpy(b->d_probs, hp.data(), sizeof(BatchProb) * nprob, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->d_order, order.data(), sizeof(int) * nprob, hipMemcpyHostToDevice) != hipSuccess)
-        return bail(ENOMR_EHIP, "cannot upload batch descriptors");
+    if (b->nprob > 0) {
+        if (hipMalloc(&b->d_probs, sizeof(BatchProb) * b->nprob) != hipSuccess ||
+            hipMalloc(&b->d_order, sizeof(int) * b->nprob) != hipSuccess)
+            return bail(ENOMR_ENOMEM, "cannot allocate batch descriptors");
+        if (hipMemcpy(b->d_probs, hp.data(), sizeof(BatchProb) * b->nprob, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b->d_order, order.data(), sizeof(int) * b->nprob, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(ENOMR_EHIP, "cannot upload batch descriptors");
+    }
+    if (b->nprob2 > 0) {
+        if (hipMalloc(&b->d_probs2, sizeof(BatchProb2) * b->nprob2) != hipSuccess ||
+            hipMalloc(&b->d_order2, sizeof(int) * b->nprob2) != hipSuccess)
+            return bail(ENOMR_ENOMEM, "cannot allocate batch descriptors");
+        if (hipMemcpy(b->d_probs2, hp2.data(), sizeof(BatchProb2) * b->nprob2, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b->d_order2, order2.data(), sizeof(int) * b->nprob2, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(ENOMR_EHIP, "cannot upload batch descriptors");
+        b->nblocks2 = batch_blocks2(b->nprob2);
+    }
 
-    // Autotune the tile width: one step of the whole batch on scratch copies of
-    // the states, per width; the fastest wins.
+    // Autotune the 1D kernel's tile width: one step of the 1D problems on
+    // scratch copies of their states, per width; the fastest wins.
     b->tf = 128;
     if (autotune == 64 || autotune == 128 || autotune == 256) b->tf = autotune;
-    if (autotune == 1) {
+    const int n1 = b->nprob;
+    if (autotune == 1 && n1 > 0) {
         size_t state_bytes = 0;
-        for (int i = 0; i < nprob; ++i) state_bytes += align_up(sizeof(double) * 3 * (size_t)probs[i].nx);
+        for (int k = 0; k < n1; ++k) state_bytes += align_up(sizeof(double) * 3 * (size_t)probs[i1[k]].nx);
         double* scratch = nullptr;
         BatchProb* d_tune = nullptr;
-        if (hipMalloc(&scratch, state_bytes) != hipSuccess || hipMalloc(&d_tune, sizeof(BatchProb) * nprob) != hipSuccess) {
+        if (hipMalloc(&scratch, state_bytes) != hipSuccess || hipMalloc(&d_tune, sizeof(BatchProb) * n1) != hipSuccess) {
             (void)hipFree(scratch);
             return bail(ENOMR_ENOMEM, "cannot allocate autotune scratch");
         }
         std::vector<BatchProb> tp = hp;
         size_t so = 0;
-        for (int i = 0; i < nprob; ++i) {
-            tp[i].U = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) + so);
-            so += align_up(sizeof(double) * 3 * (size_t)probs[i].nx);
+        for (int k = 0; k < n1; ++k) {
+            tp[k].U = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) + so);
+            so += align_up(sizeof(double) * 3 * (size_t)probs[i1[k]].nx);
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        bool ok = hipMemcpy(d_tune, tp.data(), sizeof(BatchProb) * nprob, hipMemcpyHostToDevice) == hipSuccess &&
+        bool ok = hipMemcpy(d_tune, tp.data(), sizeof(BatchProb) * n1, hipMemcpyHostToDevice) == hipSuccess &&
                   hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
         double best = 1e300;
         for (int t = 0; ok && t < 3; ++t) {
             const int tf = kBatchTF[t];
-            for (int i = 0; i < nprob && ok; ++i)
-                ok = hipMemcpyAsync(tp[i].U, U[i], sizeof(double) * 3 * (size_t)probs[i].nx, hipMemcpyDeviceToDevice,
-                                    ctx->stream) == hipSuccess;
-            b->nblocks = batch_blocks(tf, nprob);
+            for (int k = 0; k < n1 && ok; ++k)
+                ok = hipMemcpyAsync(tp[k].U, U[i1[k]], sizeof(double) * 3 * (size_t)probs[i1[k]].nx,
+                                    hipMemcpyDeviceToDevice, ctx->stream) == hipSuccess;
+            b->nblocks = batch_blocks(tf, n1);
             hipLaunchKernelGGL(k_set_batch_params, dim3(1), dim3(64), 0, ctx->stream, b->d_params, 0.5, 1L, b->d_queue);
             ok = ok && hipEventRecord(e0, ctx->stream) == hipSuccess;
             ok = ok && launch_batch(b, tf, d_tune, ctx->stream) == hipSuccess;
@@ -975,14 +1053,35 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
         if (!ok) return bail(ENOMR_EHIP, "autotune failed");
         // the autotune steps may have latched a status; keep it for enomr_check
     }
-    b->nblocks = batch_blocks(b->tf, nprob);
+    if (n1 > 0) b->nblocks = batch_blocks(b->tf, n1);
 
-    // Capture the persistent launch into a graph, replayed by every advance.
-    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
-        return bail(ENOMR_EHIP, "cannot create capture stream");
+    // Capture the persistent launches into a graph, replayed by every advance.
+    // With both kinds of problems the 2D kernel runs beside the 1D one: the
+    // second stream forks from the capture stream before either launch.
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->cap2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)
+        return bail(ENOMR_EHIP, "cannot create capture streams");
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bail(ENOMR_EHIP, "cannot begin capture");
-    hipError_t le = launch_batch(b, b->tf, b->d_probs, b->cap);
+    hipError_t le = hipSuccess;
+    const bool both = n1 > 0 && b->nprob2 > 0;
+    hipStream_t s2 = both ? b->cap2 : b->cap;
+    if (both) {
+        if (le == hipSuccess) le = hipEventRecord(b->fork, b->cap);
+        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap2, b->fork, 0);
+    }
+    if (le == hipSuccess && n1 > 0) le = launch_batch(b, b->tf, b->d_probs, b->cap);
+    if (le == hipSuccess && b->nprob2 > 0) {
+        hipLaunchKernelGGL(k_batch_euler2d, dim3(b->nblocks2), dim3(kB2TF * kB2TL), 0, s2, b->d_probs2, b->d_order2,
+                           b->nprob2, b->d_queue + 1, b->d_params, ctx->status);
+        le = hipGetLastError();
+    }
+    if (both) {
+        if (le == hipSuccess) le = hipEventRecord(b->join, b->cap2);
+        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap, b->join, 0);
+    }
     hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
     if (le != hipSuccess || ce != hipSuccess) return bail(ENOMR_EHIP, "capture of the batch launch failed");
     if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
@@ -1007,7 +1106,7 @@ enomr_status enomr_batch_info(const enomr_batch* b, int32_t* tile_faces, int32_t
 {
     if (!b) return fail(ENOMR_EINVAL, "batch is NULL");
     if (tile_faces) *tile_faces = b->tf;
-    if (workgroups) *workgroups = (int32_t)b->nblocks;
+    if (workgroups) *workgroups = (int32_t)(b->nblocks + b->nblocks2);
     if (tune_ms)
         for (int i = 0; i < 3; ++i) tune_ms[i] = b->tune_ms[i];
     return ENOMR_OK;

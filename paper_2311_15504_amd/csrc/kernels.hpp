@@ -766,12 +766,14 @@ struct BatchParams {
     long nsteps;
 };
 
+// queue: the work counters of the 1D and the 2D kernel
 __global__ void k_set_batch_params(BatchParams* p, double cfl, long nsteps, int* queue)
 {
     if (threadIdx.x == 0) {
         p->cfl = cfl;
         p->nsteps = nsteps;
-        *queue = 0;
+        queue[0] = 0;
+        queue[1] = 0;
     }
 }
 
@@ -866,6 +868,173 @@ __global__ __launch_bounds__(TF, 4) void k_batch_euler1d(const BatchProb* __rest
         case 7: run_problem<7, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
         case 8: run_problem<8, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
         default: run_problem<9, TF>(pr, P, status, lds_raw, red, &s_alpha, &s_dt); break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched 2D Euler problems: one 256-thread workgroup advances a whole
+// problem, each stage as per-line alphas (a wave per row, then per column),
+// dt at the first stage, the x sweep into L_x and the y sweep with the RK
+// combination, over the same 64 x 4 tiles as the single-problem kernels, so
+// every problem's result equals its single-problem run bit for bit.
+// ---------------------------------------------------------------------------
+
+struct BatchProb2 {
+    double* U;       // [4][ny][nx] state, advanced in place
+    double* U1;      // stage states (workspace)
+    double* U2;
+    double* L;       // L_x (workspace)
+    double* ax;      // [ny] alphas of the rows
+    double* ay;      // [nx] alphas of the columns
+    long nx, ny;
+    double ihx, ihy;
+    double gamma;
+    int R;
+    int bcx, bcy;
+};
+
+// Per-line |u|+c (rows, into ax) and |v|+c (columns, into ay), each line's
+// maximum taken by one wave; the same speed formula as k_alpha_euler.
+__device__ __forceinline__ void block_line_speeds_2d(const double* __restrict__ U, long nx, long ny, double gamma,
+                                                     unsigned* status, double* ax, double* ay)
+{
+    const long plane = nx * ny;
+    const double gm1 = gamma - 1.0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    auto speeds = [&](long g, bool flag, double& sx, double& sy) {
+        const double rho = U[g], m = U[plane + g], nn = U[2 * plane + g], E = U[3 * plane + g];
+        const double ir = 1.0 / rho;
+        const double u = m * ir;
+        const double v = nn * ir;
+        const double ke = 0.5 * (m * u + nn * v);
+        const double p = gm1 * (E - ke);
+        if (flag && (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(m) || !isfinite(nn)))
+            flag_nonphysical(status);
+        const double c = sqrt((gamma * p) * ir);
+        sx = fabs(u) + c;
+        sy = fabs(v) + c;
+    };
+    for (long y = wave; y < ny; y += nw) {
+        double mx = 0.0;
+        for (long x = lane; x < nx; x += 64) {
+            double sx, sy;
+            speeds(y * nx + x, true, sx, sy);
+            mx = fmax(mx, sx);
+        }
+        mx = wave_max(mx);
+        if (lane == 0) ax[y] = mx;
+    }
+    for (long x = wave; x < nx; x += nw) {
+        double my = 0.0;
+        for (long y = lane; y < ny; y += 64) {
+            double sx, sy;
+            speeds(y * nx + x, false, sx, sy);
+            my = fmax(my, sy);
+        }
+        my = wave_max(my);
+        if (lane == 0) ay[x] = my;
+    }
+}
+
+constexpr int kB2TF = 64, kB2TL = 4, kB2NCL = kB2TF + 17;   // the single-problem 2D tile shape
+
+template <int R>
+__device__ __forceinline__ void run_problem_2d(const BatchProb2& P, const BatchParams& prm, unsigned* status,
+                                               char* lds_raw, double* red, double* s_dt)
+{
+    using Lds = SweepLds<4, kB2NCL * kB2TL, kB2TF * kB2TL>;
+    Lds& sm = *reinterpret_cast<Lds*>(lds_raw);
+    const long nx = P.nx, ny = P.ny;
+    for (long step = 0; step < prm.nsteps; ++step) {
+        for (int stage = 1; stage <= 3; ++stage) {
+            const double* Us = stage == 1 ? P.U : (stage == 2 ? P.U1 : P.U2);
+            double* out = stage == 1 ? P.U1 : (stage == 2 ? P.U2 : P.U);
+            block_line_speeds_2d(Us, nx, ny, P.gamma, status, P.ax, P.ay);
+            __syncthreads();
+            if (stage == 1) {
+                double mx = 0.0, my = 0.0;
+                for (long i = threadIdx.x; i < ny; i += blockDim.x) mx = fmax(mx, P.ax[i]);
+                for (long i = threadIdx.x; i < nx; i += blockDim.x) my = fmax(my, P.ay[i]);
+                mx = wave_max(mx);
+                my = wave_max(my);
+                if ((threadIdx.x & 63) == 0) {
+                    red[threadIdx.x >> 6] = mx;
+                    red[4 + (threadIdx.x >> 6)] = my;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+                    my = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+                    *s_dt = prm.cfl / (mx * P.ihx + my * P.ihy);
+                }
+                __syncthreads();
+            }
+            SweepIn in;
+            in.Us = Us;
+            in.status = status;
+            in.idx = nullptr;
+            in.active = nullptr;
+            in.nx = nx;
+            in.ny = ny;
+            in.gamma = P.gamma;
+            // x sweep: L_x into P.L
+            in.alpha = P.ax;
+            in.ih = P.ihx;
+            in.bc = P.bcx;
+            StageOut sx;
+            sx.Un = nullptr;
+            sx.Lprev = nullptr;
+            sx.out = P.L;
+            sx.dt = nullptr;
+            sx.stage = 0;
+            for (long l0 = 0; l0 < ny; l0 += kB2TL)
+                for (long c0 = 0; c0 < nx; c0 += kB2TF - 1)
+                    sweep_tile<4, R, 0, kB2TF, kB2TL, kB2NCL>(in, sx, l0, c0, sm);
+            __syncthreads();
+            // y sweep: adds L_y and combines the RK stage
+            in.alpha = P.ay;
+            in.ih = P.ihy;
+            in.bc = P.bcy;
+            StageOut sy;
+            sy.Un = P.U;
+            sy.Lprev = P.L;
+            sy.out = out;
+            sy.dt = s_dt;
+            sy.stage = stage;
+            for (long l0 = 0; l0 < nx; l0 += kB2TL)
+                for (long c0 = 0; c0 < ny; c0 += kB2TF - 1)
+                    sweep_tile<4, R, 1, kB2TF, kB2TL, kB2NCL>(in, sy, l0, c0, sm);
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kB2TF * kB2TL, 4) void k_batch_euler2d(const BatchProb2* __restrict__ probs,
+                                                                     const int* __restrict__ order, int nprob,
+                                                                     int* queue, const BatchParams* prm,
+                                                                     unsigned* status)
+{
+    __shared__ __align__(16) char lds_raw[sizeof(SweepLds<4, kB2NCL * kB2TL, kB2TF * kB2TL>)];
+    __shared__ double red[8];
+    __shared__ double s_dt;
+    __shared__ int s_k;
+    const BatchParams P = *prm;
+    for (;;) {
+        if (threadIdx.x == 0) s_k = atomicAdd(queue, 1);
+        __syncthreads();
+        const int k = s_k;
+        __syncthreads();
+        if (k >= nprob) return;   // the whole workgroup leaves together
+        const BatchProb2 pr = probs[order[k]];
+        switch (pr.R) {
+        case 3: run_problem_2d<3>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 4: run_problem_2d<4>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 5: run_problem_2d<5>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 6: run_problem_2d<6>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 7: run_problem_2d<7>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 8: run_problem_2d<8>(pr, P, status, lds_raw, red, &s_dt); break;
+        default: run_problem_2d<9>(pr, P, status, lds_raw, red, &s_dt); break;
         }
     }
 }

@@ -85,6 +85,46 @@ def test_batch_multi_tile_problems_each_width(ctx, tf):
     batch.close()
 
 
+def _problems_2d(nprob, seed):
+    import paper_2311_15504_amd as enomr
+    rng = np.random.default_rng(seed)
+    probs, data = [], []
+    for i in range(nprob):
+        order = int(rng.choice([5, 9, 13, 17]))
+        r = (order + 1) // 2
+        nx = int(rng.integers(2 * r + 1, 150))
+        ny = int(rng.integers(2 * r + 1, 110))
+        (x, y, hx, hy), U = workloads.euler2d_quadrants_vortices(seed * 100 + i, nx, ny)
+        bcx = enomr.PERIODIC if i % 3 else enomr.OUTFLOW
+        bcy = enomr.OUTFLOW if i % 2 else enomr.PERIODIC
+        probs.append(enomr.Problem.euler2d(nx, ny, hx, hy, order, bcx, bcy))
+        data.append(U)
+    return probs, data
+
+
+@pytest.mark.parametrize("with_1d", [True, False])
+def test_batch_2d_problems_equal_single_problem_runs_bitwise(ctx, with_1d):
+    # 2D problems of uneven sizes, orders and boundaries, alone or beside 1D
+    # problems (the two kernels then run side by side in one graph).
+    import torch
+    import paper_2311_15504_amd as enomr
+    probs, data = _problems_2d(9, 3)
+    if with_1d:
+        p1, d1 = _problems(11, 4)
+        probs, data = p1 + probs, d1 + data
+    states = [torch.from_numpy(U).cuda() for U in data]
+    batch = enomr.Batch(ctx, probs, states, autotune=with_1d)
+    batch.advance(0.5, 4)
+    batch.advance(0.5, 2)
+    ctx.check()
+    for p, U0, Ub in zip(probs, data, states):
+        Us = torch.from_numpy(U0).cuda()
+        ctx.advance(p, Us, 0.5, 6)
+        ctx.check()
+        assert torch.equal(Ub, Us), (p.ndim, p.nx, p.ny, p.order, p.bc_x, p.bc_y)
+    batch.close()
+
+
 def test_batch_matches_oracle(ctx):
     import torch
     import paper_2311_15504_amd as enomr
@@ -104,10 +144,10 @@ def test_batch_matches_oracle(ctx):
 def test_batch_rejects_bad_problems(ctx):
     import torch
     import paper_2311_15504_amd as enomr
-    (x, y, hx, hy), U2 = workloads.euler2d_quadrants_vortices(0, 32, 32)
-    p2 = enomr.Problem.euler2d(32, 32, hx, hy, 5)
+    _, h, u = workloads.advection_sines_step(1, 64)
+    ps = enomr.Problem.scalar(enomr.ADVECTION, 64, h, 5)
     with pytest.raises(enomr.EnomrError):
-        enomr.Batch(ctx, [p2], [torch.from_numpy(U2).cuda()])
+        enomr.Batch(ctx, [ps], [torch.from_numpy(u[None]).cuda()])
     _, h, U1 = workloads.euler1d_riemann_perturbed(0, 100)
     p1 = enomr.Problem.euler1d(100, h, 9)
     with pytest.raises(enomr.EnomrError):

@@ -152,6 +152,25 @@ def batched_problems(seed, nprob=4096, nmin=256, nmax=16384, orders=(7, 9, 13, 1
     return out
 
 
+def batched_problems_2d(seed, nprob=256, nmin=32, nmax=192, orders=(7, 9, 13, 17)):
+    """Seeded list of independent 2D Euler problems of uneven sizes and orders.
+
+    Returns a list of dicts {nx, ny, order, hx, hy, U}; each problem's data
+    follows euler2d_quadrants_vortices with its own child seed.
+    """
+    ss = np.random.SeedSequence(seed)
+    out = []
+    for child in ss.spawn(nprob):
+        rng = np.random.default_rng(child)
+        nx = int(rng.integers(nmin, nmax + 1))
+        ny = int(rng.integers(nmin, nmax + 1))
+        order = int(orders[int(rng.integers(0, len(orders)))])
+        sub = int(rng.integers(0, 2**31 - 1))
+        (x, y, hx, hy), U = euler2d_quadrants_vortices(sub, nx, ny)
+        out.append({"nx": nx, "ny": ny, "order": order, "hx": hx, "hy": hy, "U": U})
+    return out
+
+
 # --------------------------------------------------------------------------
 # 2D Euler
 # --------------------------------------------------------------------------
