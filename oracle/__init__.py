@@ -77,6 +77,14 @@ def lib():
         L.orc_euler2d_rhs.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_long, ctypes.c_long, ctypes.c_double, ctypes.c_double,
                                       _dp, _dp, _u8p, _u8p, _dp, _dp]
+        L.orc_euler1d_rhs_var.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_long,
+                                          ctypes.c_double, _dp, _dp, _u8p, _dp, ctypes.c_int, ctypes.c_int]
+        L.orc_euler1d_rhs_var.restype = ctypes.c_int
+        L.orc_euler2d_rhs_var.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_long, ctypes.c_long, ctypes.c_double, ctypes.c_double,
+                                          _dp, _dp, _u8p, _u8p, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double]
+        L.orc_euler2d_rhs_var.restype = ctypes.c_int
         L.orc_euler2d_rhs_cells.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_long, ctypes.c_long, ctypes.c_double, ctypes.c_double,
                                             _dp, ctypes.c_long, _lp, _dp]
@@ -231,6 +239,20 @@ def euler1d_rhs(order, U, h, gamma=1.4, bc=OUTFLOW, with_idx=False):
     return out
 
 
+def euler1d_rhs_var(order, U, h, gamma=1.4, bc=OUTFLOW, componentwise=False, per_field=False):
+    """1D Euler L(U) with the operator variants (component-wise reconstruction
+    or per-field alphas, see enomr_oracle.c).  Returns (L, idx [n+1][3][2],
+    alphas: one value, or three per-field values)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    n = U.shape[1]
+    out = np.empty_like(U)
+    idx = np.empty((n + 1) * 6, dtype=np.uint8)
+    alpha = np.zeros(3)
+    _check(lib().orc_euler1d_rhs_var(table(order), gamma, bc, n, 1.0 / h, _p(U), _p(out), _u8(idx), _p(alpha),
+                                     int(componentwise), int(per_field)), "euler1d_rhs_var")
+    return out, idx.reshape(n + 1, 3, 2), (alpha if per_field else alpha[:1])
+
+
 def euler1d_rhs_frozen(order, U, h, idx, alpha, dU=None, gamma=1.4, bc=OUTFLOW):
     """Frozen-stencil operator L(U; idx, alpha) and, if dU is given, its
     tangent dL/dU . dU (dual numbers).  Returns L or (L, dL)."""
@@ -272,6 +294,25 @@ def euler2d_rhs(order, U, hx, hy, gamma=1.4, bcx=PERIODIC, bcy=OUTFLOW, with_idx
     if with_idx:
         return out, ix.reshape(ny, nx + 1, 4, 2), iy.reshape(ny + 1, nx, 4, 2), ax, ay
     return out
+
+
+def euler2d_rhs_var(order, U, hx, hy, gamma=1.4, bcx=PERIODIC, bcy=OUTFLOW, componentwise=False,
+                    per_field=False, gravity=0.0):
+    """2D Euler L(U) with the operator variants (component-wise reconstruction,
+    per-field alphas, gravity source g [0, 0, rho, rho v]).  Returns
+    (L, ix, iy, ax, ay); with per_field ax is [3][ny] and ay [3][nx]."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    _, ny, nx = U.shape
+    out = np.empty_like(U)
+    ix = np.empty(ny * (nx + 1) * 8, dtype=np.uint8)
+    iy = np.empty((ny + 1) * nx * 8, dtype=np.uint8)
+    na = 3 if per_field else 1
+    ax = np.empty((na, ny))
+    ay = np.empty((na, nx))
+    _check(lib().orc_euler2d_rhs_var(table(order), gamma, bcx, bcy, nx, ny, 1.0 / hx, 1.0 / hy, _p(U), _p(out),
+                                     _u8(ix), _u8(iy), _p(ax), _p(ay), int(componentwise), int(per_field),
+                                     float(gravity)), "euler2d_rhs_var")
+    return out, ix.reshape(ny, nx + 1, 4, 2), iy.reshape(ny + 1, nx, 4, 2), ax, ay
 
 
 def euler2d_rhs_ops(order, U, hx, hy, gamma=1.4, bcx=PERIODIC, bcy=OUTFLOW):
@@ -340,16 +381,21 @@ def euler1d_run(order, U0, h, nsteps, cfl=0.5, gamma=1.4, bc=OUTFLOW, dts=None):
     return U, used
 
 
-def euler2d_run(order, U0, hx, hy, nsteps, cfl=0.5, gamma=1.4, bcx=PERIODIC, bcy=OUTFLOW):
+def euler2d_run(order, U0, hx, hy, nsteps, cfl=0.5, gamma=1.4, bcx=PERIODIC, bcy=OUTFLOW, componentwise=False,
+                per_field=False, gravity=0.0):
     U = np.array(U0, dtype=np.float64, copy=True)
     used = []
+    plain = not (componentwise or per_field or gravity)
     for step in range(nsteps):
         dt = dt_2d(U, hx, hy, cfl, gamma)
         used.append(dt)
         un = U.copy()
         us = U.copy()
         for s in (1, 2, 3):
-            L = euler2d_rhs(order, us, hx, hy, gamma, bcx, bcy)
+            if plain:
+                L = euler2d_rhs(order, us, hx, hy, gamma, bcx, bcy)
+            else:
+                L = euler2d_rhs_var(order, us, hx, hy, gamma, bcx, bcy, componentwise, per_field, gravity)[0]
             us = ssprk3_combine(s, un, us, L, dt)
         U = us
     return U, used

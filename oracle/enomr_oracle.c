@@ -33,6 +33,18 @@
  *   linear SSP-RK(m, m-1) ....................... Sec. 2.3, Eqs. (lSSPRK), (lSSPRK_Coe)
  *   Euler equations, characteristic projection .. Sec. 4 preamble (Roe average at the
  *                                                 face), Sec. 4.3, Sec. 4.4
+ *
+ * Variants of the Euler operator (each off by default):
+ *   component-wise reconstruction: the split fluxes G+- of each conserved
+ *     component are reconstructed as they are, with no projection (the
+ *     scalar procedure applied to a system component by component);
+ *   per-field alpha: each characteristic field k splits with its own
+ *     alpha_k = max over the line of |lambda_k| (lambda = u-c, u, [u,] u+c),
+ *     a field-wise reading of the maximum of Eq. (LF_Flux_Split);
+ *     w+-_k = (l_k.F +- alpha_k l_k.U) / 2, each product l_k.x by the
+ *     projection chain, then t = alpha_k (l_k.U), w+- = 0.5 (l_k.F +- t);
+ *   gravity: the source g [0, 0, rho, rho v] of the Rayleigh-Taylor problem
+ *     (Sec. 4.4) added to the 2D right-hand side after the two sweeps.
  */
 #include <math.h>
 #include <stdint.h>
@@ -460,12 +472,51 @@ static int line_alpha(int nv, double gamma, long n, const double *Ul, double *al
 }
 
 /*
+ * Per-field alphas of one line: a[0] = max |u_n - c|, a[1] = max |u_n|,
+ * a[2] = max |u_n + c| over its n cells (the characteristic speeds of the
+ * fields u-c, u (and the shear field) and u+c).
+ */
+static int line_alpha_fields(int nv, double gamma, long n, const double *Ul, double a[3])
+{
+    a[0] = a[1] = a[2] = 0.0;
+    for (long i = 0; i < n; ++i) {
+        double U[4];
+        for (int v = 0; v < nv; ++v) U[v] = Ul[v * n + i];
+        cell_prim q;
+        if (primitives(nv, gamma, U, &q)) return ORC_ENONPHYS;
+        double s0 = fabs(q.un - q.c), s1 = fabs(q.un), s2 = fabs(q.un + q.c);
+        if (s0 > a[0]) a[0] = s0;
+        if (s1 > a[1]) a[1] = s1;
+        if (s2 > a[2]) a[2] = s2;
+    }
+    return ORC_OK;
+}
+
+/* Which of the three per-field alphas field k of an nv-field system uses. */
+static int field_speed(int nv, int k)
+{
+    if (k == 0) return 0;
+    if (k == nv - 1) return 2;
+    return 1;
+}
+
+/* Operator variants (see the header comment). */
+typedef struct {
+    int componentwise;
+    int per_field;
+} euler_var;
+
+static const euler_var k_default_var = {0, 0};
+
+/*
  * Numerical fluxes at faces f = 0..n of one line (face f between cells f-1
  * and f).  Ul is [nv][n] in the face-normal frame.  Fhat is [n+1][nv].
+ * alpha: the line's alpha, or its three per-field alphas (var.per_field).
  * idx (optional) holds nv*2 entries per face: [(field)*2 + (0:+, 1:-)].
  */
 static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, long n,
-                             const double *Ul, double alpha, double *Fhat, uint8_t *idx)
+                             const double *Ul, const double *alpha, euler_var var, double *Fhat,
+                             uint8_t *idx)
 {
     const long g = T->r + 1;
     const long nn = n + 2 * g;
@@ -477,15 +528,18 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
     double *wm = (double *)malloc(sizeof(double) * nn);
     int st = ORC_OK;
     const int counting = g_counting;
+    /* the operation counter covers the default operator only */
+    if (var.componentwise || var.per_field) g_counting = 0;
     if (!U || !Gp || !Gm || !Q || !wp || !wm) { st = ORC_EINVAL; goto done; }
 
-    /* Ghosted line, primitive quantities and the LF split G = (F +- alpha U)/2. */
+    /* Ghosted line, primitive quantities and the LF split G = (F +- alpha U)/2
+       (with per-field alphas the split is taken after the projection). */
     for (long i = 0; i < nn; ++i) {
         long src = map_cell(i - g, n, bc);
         for (int v = 0; v < nv; ++v) U[i * nv + v] = Ul[v * n + src];
         if ((st = primitives(nv, gamma, &U[i * nv], &Q[i]))) goto done;
         for (int v = 0; v < nv; ++v) {
-            double t = alpha * U[i * nv + v];
+            double t = alpha[0] * U[i * nv + v];
             Gp[i * nv + v] = 0.5 * (Q[i].F[v] + t);
             Gm[i * nv + v] = 0.5 * (Q[i].F[v] - t);
         }
@@ -499,7 +553,25 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
         long j = f - 1 + g;      /* left cell of the face in the ghosted line */
         double Lm[4][4], Rm[4][4];
         /* a periodic line's face n is its face 0 again: counted once */
-        g_counting = counting && !(bc == ORC_PERIODIC && f == n);
+        g_counting = counting && !var.componentwise && !var.per_field && !(bc == ORC_PERIODIC && f == n);
+        if (var.componentwise) {
+            /* G+- of each component reconstructed as they are */
+            for (int k = 0; k < nv; ++k) {
+                for (long i = j - T->r + 1; i <= j + T->r; ++i) {
+                    wp[i] = Gp[i * nv + k];
+                    wm[i] = Gm[i * nv + k];
+                }
+                int kp, km;
+                double hp = recon_face(T, wp, j, +1, &kp);
+                double hm = recon_face(T, wm, j, -1, &km);
+                Fhat[f * nv + k] = hp + hm;
+                if (idx) {
+                    idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
+                    idx[(f * nv + k) * 2 + 1] = (uint8_t)km;
+                }
+            }
+            continue;
+        }
         if ((st = roe_eigen(nv, gamma, &U[j * nv], &Q[j], &U[(j + 1) * nv], &Q[j + 1], Lm, Rm)))
             goto done;
         /* Roe average and the entries of L and R used below (0.5 q^2 is shared
@@ -512,9 +584,19 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
         double what[4];
         for (int k = 0; k < nv; ++k) {
             /* characteristic field k of the split fluxes over the face's window */
-            for (long i = j - T->r + 1; i <= j + T->r; ++i) {
-                wp[i] = project_dot(Lm[k], &Gp[i * nv], nv);
-                wm[i] = project_dot(Lm[k], &Gm[i * nv], nv);
+            if (var.per_field) {
+                const double ak = alpha[field_speed(nv, k)];
+                for (long i = j - T->r + 1; i <= j + T->r; ++i) {
+                    double pf = project_dot(Lm[k], Q[i].F, nv);
+                    double t = ak * project_dot(Lm[k], &U[i * nv], nv);
+                    wp[i] = 0.5 * (pf + t);
+                    wm[i] = 0.5 * (pf - t);
+                }
+            } else {
+                for (long i = j - T->r + 1; i <= j + T->r; ++i) {
+                    wp[i] = project_dot(Lm[k], &Gp[i * nv], nv);
+                    wm[i] = project_dot(Lm[k], &Gm[i * nv], nv);
+                }
             }
             int kp, km;
             double hp = recon_face(T, wp, j, +1, &kp);
@@ -535,18 +617,33 @@ done:
     return st;
 }
 
-/* 1D Euler right-hand side L(U), U and dUdt laid out [3][n]. */
-int orc_euler1d_rhs(const orc_table *T, double gamma, int bc, long n, double ih,
-                    const double *U, double *dUdt, uint8_t *idx, double *alpha_out)
+/* A line's alpha (one value) or per-field alphas (three values). */
+static int line_alphas(int nv, double gamma, long n, const double *Ul, euler_var var, double a[3])
 {
-    if (!T || n < 2) return ORC_EINVAL;
-    double alpha;
-    int st = line_alpha(3, gamma, n, U, &alpha);
+    if (var.per_field) return line_alpha_fields(nv, gamma, n, Ul, a);
+    a[1] = a[2] = 0.0;
+    return line_alpha(nv, gamma, n, Ul, &a[0]);
+}
+
+/*
+ * 1D Euler right-hand side L(U), U and dUdt laid out [3][n], with the
+ * variant switches componentwise and per_field (not both).  alpha_out
+ * (optional) receives the line's alpha, or its three per-field alphas.
+ */
+int orc_euler1d_rhs_var(const orc_table *T, double gamma, int bc, long n, double ih,
+                        const double *U, double *dUdt, uint8_t *idx, double *alpha_out,
+                        int componentwise, int per_field)
+{
+    if (!T || n < 2 || (componentwise && per_field)) return ORC_EINVAL;
+    euler_var var = {componentwise != 0, per_field != 0};
+    double alpha[3];
+    int st = line_alphas(3, gamma, n, U, var, alpha);
     if (st) return st;
-    if (alpha_out) *alpha_out = alpha;
+    if (alpha_out)
+        for (int k = 0; k < (per_field ? 3 : 1); ++k) alpha_out[k] = alpha[k];
     double *Fh = (double *)malloc(sizeof(double) * (n + 1) * 3);
     if (!Fh) return ORC_EINVAL;
-    st = euler_line_fluxes(T, 3, gamma, bc, n, U, alpha, Fh, idx);
+    st = euler_line_fluxes(T, 3, gamma, bc, n, U, alpha, var, Fh, idx);
     if (!st)
         for (int v = 0; v < 3; ++v)
             for (long i = 0; i < n; ++i)
@@ -555,19 +652,32 @@ int orc_euler1d_rhs(const orc_table *T, double gamma, int bc, long n, double ih,
     return st;
 }
 
+/* 1D Euler right-hand side L(U), U and dUdt laid out [3][n]. */
+int orc_euler1d_rhs(const orc_table *T, double gamma, int bc, long n, double ih,
+                    const double *U, double *dUdt, uint8_t *idx, double *alpha_out)
+{
+    return orc_euler1d_rhs_var(T, gamma, bc, n, ih, U, dUdt, idx, alpha_out, 0, 0);
+}
+
 /*
  * 2D Euler right-hand side, dimension by dimension (Sec. 2.1):
  * dU/dt = -(F_{i+1/2} - F_{i-1/2})/hx - (G_{j+1/2} - G_{j-1/2})/hy.
  * U, dUdt: [4][ny][nx].  x-lines use (rho, m, n, E); y-lines the permuted
  * state (rho, n, m, E) so that the same normal-frame formulas apply.
  * idx_x (optional): [ny][nx+1][4][2]; idx_y (optional): [ny+1][nx][4][2].
- * alpha_x[ny], alpha_y[nx] (optional) receive the per-line alphas.
+ * alpha_x[ny], alpha_y[nx] (optional) receive the per-line alphas; with
+ * per_field, alpha_x[3][ny] and alpha_y[3][nx] the per-field ones.
+ * componentwise, per_field (not both): the variants of the header comment;
+ * gravity g != 0 adds the source g [0, 0, rho, rho v] to the result.
  */
-int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny,
-                    double ihx, double ihy, const double *U, double *dUdt,
-                    uint8_t *idx_x, uint8_t *idx_y, double *alpha_x, double *alpha_y)
+int orc_euler2d_rhs_var(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny,
+                        double ihx, double ihy, const double *U, double *dUdt,
+                        uint8_t *idx_x, uint8_t *idx_y, double *alpha_x, double *alpha_y,
+                        int componentwise, int per_field, double gravity)
 {
-    if (!T || nx < 2 || ny < 2) return ORC_EINVAL;
+    if (!T || nx < 2 || ny < 2 || (componentwise && per_field)) return ORC_EINVAL;
+    euler_var var = {componentwise != 0, per_field != 0};
+    const int na = per_field ? 3 : 1;
     const long plane = nx * ny;
     long nmax = nx > ny ? nx : ny;
     double *line = (double *)malloc(sizeof(double) * 4 * nmax);
@@ -581,10 +691,11 @@ int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx,
     for (long y = 0; y < ny; ++y) {
         for (int v = 0; v < 4; ++v)
             for (long x = 0; x < nx; ++x) line[v * nx + x] = U[v * plane + y * nx + x];
-        double alpha;
-        if ((st = line_alpha(4, gamma, nx, line, &alpha))) goto done;
-        if (alpha_x) alpha_x[y] = alpha;
-        if ((st = euler_line_fluxes(T, 4, gamma, bcx, nx, line, alpha, Fh, idx_x ? idl : NULL)))
+        double alpha[3];
+        if ((st = line_alphas(4, gamma, nx, line, var, alpha))) goto done;
+        if (alpha_x)
+            for (int k = 0; k < na; ++k) alpha_x[k * ny + y] = alpha[k];
+        if ((st = euler_line_fluxes(T, 4, gamma, bcx, nx, line, alpha, var, Fh, idx_x ? idl : NULL)))
             goto done;
         if (idx_x) memcpy(idx_x + (size_t)y * (nx + 1) * 8, idl, (size_t)(nx + 1) * 8);
         for (int v = 0; v < 4; ++v)
@@ -597,10 +708,11 @@ int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx,
     for (long x = 0; x < nx; ++x) {
         for (int v = 0; v < 4; ++v)
             for (long y = 0; y < ny; ++y) line[v * ny + y] = U[perm[v] * plane + y * nx + x];
-        double alpha;
-        if ((st = line_alpha(4, gamma, ny, line, &alpha))) goto done;
-        if (alpha_y) alpha_y[x] = alpha;
-        if ((st = euler_line_fluxes(T, 4, gamma, bcy, ny, line, alpha, Fh, idx_y ? idl : NULL)))
+        double alpha[3];
+        if ((st = line_alphas(4, gamma, ny, line, var, alpha))) goto done;
+        if (alpha_y)
+            for (int k = 0; k < na; ++k) alpha_y[k * nx + x] = alpha[k];
+        if ((st = euler_line_fluxes(T, 4, gamma, bcy, ny, line, alpha, var, Fh, idx_y ? idl : NULL)))
             goto done;
         if (idx_y)
             for (long f = 0; f <= ny; ++f) memcpy(idx_y + ((size_t)f * nx + x) * 8, idl + f * 8, 8);
@@ -612,9 +724,24 @@ int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx,
             }
         OPS(12 * ny);
     }
+    /* source term of the Rayleigh-Taylor problem (Sec. 4.4): rho g in the
+       y-momentum, rho v g in the energy equation */
+    if (gravity != 0.0)
+        for (long i = 0; i < plane; ++i) {
+            dUdt[2 * plane + i] = dUdt[2 * plane + i] + gravity * U[i];
+            dUdt[3 * plane + i] = dUdt[3 * plane + i] + gravity * U[2 * plane + i];
+        }
 done:
     free(line); free(Fh); free(idl); free(Lx);
     return st;
+}
+
+int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny,
+                    double ihx, double ihy, const double *U, double *dUdt,
+                    uint8_t *idx_x, uint8_t *idx_y, double *alpha_x, double *alpha_y)
+{
+    return orc_euler2d_rhs_var(T, gamma, bcx, bcy, nx, ny, ihx, ihy, U, dUdt, idx_x, idx_y, alpha_x,
+                               alpha_y, 0, 0, 0.0);
 }
 
 /*
@@ -649,12 +776,12 @@ int orc_euler2d_rhs_cells(const orc_table *T, double gamma, int bcx, int bcy, lo
                     int sv = dir == 0 ? v : perm[v];
                     line[v * n + i] = U[sv * plane + gy * nx + gx];
                 }
-            double alpha;
-            if ((st = line_alpha(4, gamma, n, line, &alpha))) goto done;
+            double alpha[3] = {0.0, 0.0, 0.0};
+            if ((st = line_alpha(4, gamma, n, line, &alpha[0]))) goto done;
             /* fluxes at the cell's two faces: evaluate on the whole line (plain) */
             double *Fl = (double *)malloc(sizeof(double) * 4 * (n + 1));
             if (!Fl) { st = ORC_EINVAL; goto done; }
-            st = euler_line_fluxes(T, 4, gamma, bc, n, line, alpha, Fl, NULL);
+            st = euler_line_fluxes(T, 4, gamma, bc, n, line, alpha, k_default_var, Fl, NULL);
             if (st) { free(Fl); goto done; }
             for (int v = 0; v < 4; ++v) {
                 double ih = dir == 0 ? ihx : ihy;

@@ -246,3 +246,20 @@ def euler2d_quadrants_vortices(seed, nx=2048, ny=None, nvort=8, gamma=GAMMA):
     u = u + du
     v = v + dv
     return (x, y, hx, hy), conserved_2d(rho, u, v, p, gamma)
+
+
+def euler2d_rayleigh_taylor(nx=64, ny=256, gamma=5.0 / 3.0):
+    """Rayleigh-Taylor initial data on [0, 0.25] x [0, 1] (Sec. 4.4): heavy
+    fluid (rho = 2, p = 2y + 1) below y = 1/2, light (rho = 1, p = y + 3/2)
+    above, u = 0, v = -0.025 c cos(8 pi x) with c the local sound speed.
+    In hydrostatic balance with the source [0, 0, rho, rho v] (g = 1).
+    Returns ((x, y, hx, hy), U)."""
+    x, hx = nodes(0.0, 0.25, nx)
+    y, hy = nodes(0.0, 1.0, ny)
+    X, Y = np.meshgrid(x, y)
+    low = Y < 0.5
+    rho = np.where(low, 2.0, 1.0)
+    p = np.where(low, 2.0 * Y + 1.0, Y + 1.5)
+    c = np.sqrt(gamma * p / rho)
+    v = -0.025 * c * np.cos(8.0 * math.pi * X)
+    return (x, y, hx, hy), conserved_2d(rho, np.zeros_like(X), v, p, gamma)
