@@ -536,7 +536,7 @@ def main():
         out["order13"] = {k: o13[k] for k in ("value", "unit", "ms_per_step", "kernels_ms_per_step")}
         out["order13"]["roofline_frac"] = o13["roofline"]["frac"] if o13.get("roofline") else None
     out["batched"] = None if args.no_batched else run_batched(args)
-    out["batched_2d"] = None if (args.no_batched or args.no_batched_2d) else run_batched_2d(args)
+    out["batched_2d"] = None if args.no_batched_2d else run_batched_2d(args)
     out["adjoint"] = None if args.no_adjoint else run_adjoint(args)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args)
     if args.calib_copy_mib:

@@ -48,6 +48,8 @@ typedef enum {
 enum { ENOMR_ADVECTION = 0, ENOMR_BURGERS = 1, ENOMR_EULER = 2 };
 enum { ENOMR_PERIODIC = 0, ENOMR_OUTFLOW = 1 };
 enum { ENOMR_SPLIT_NONE = 0, ENOMR_SPLIT_LF = 1 };
+enum { ENOMR_CHARACTERISTIC = 0, ENOMR_COMPONENTWISE = 1 };
+enum { ENOMR_ALPHA_LINE = 0, ENOMR_ALPHA_FIELD = 1 };
 
 /*
  * A conservation law on a uniform grid (Sec. 2.1, Eq. 1DHCL; Sec. 4.3-4.4).
@@ -65,6 +67,20 @@ enum { ENOMR_SPLIT_NONE = 0, ENOMR_SPLIT_LF = 1 };
  *            f^+, valid when f'(u) >= 0).  Euler always splits.
  *   gamma    ratio of specific heats (Euler).
  *   adv_speed  the constant a (advection).
+ * Euler operator variants (zero-initialised fields give the scheme as the
+ * paper runs it: characteristic reconstruction, one alpha per line, no
+ * source):
+ *   recon    ENOMR_CHARACTERISTIC (project G+- onto the Roe-face eigenvectors,
+ *            Sec. 4 preamble) or ENOMR_COMPONENTWISE (reconstruct each
+ *            conserved component of G+- = (F +- alpha U)/2 as it is).
+ *   alpha_mode  ENOMR_ALPHA_LINE (alpha = max over the line of |u_n|+c,
+ *            Eq. LF_Flux_Split) or ENOMR_ALPHA_FIELD (characteristic field k
+ *            splits with alpha_k = max over the line of |lambda_k|, lambda =
+ *            u_n-c, u_n, [u_n,] u_n+c: w+-_k = (l_k.F +- alpha_k l_k.U)/2).
+ *            ENOMR_ALPHA_FIELD needs ENOMR_CHARACTERISTIC.
+ *   gravity  2D Euler only: adds the source g [0, 0, rho, rho v] of the
+ *            Rayleigh-Taylor problem (Sec. 4.4) to dU/dt; 0 = no source.
+ * Batched execution and the adjoint take the default operator only.
  */
 typedef struct {
     int32_t ndim;
@@ -76,6 +92,9 @@ typedef struct {
     int32_t split;
     double gamma;
     double adv_speed;
+    int32_t recon;
+    int32_t alpha_mode;
+    double gravity;
 } enomr_problem;
 
 typedef struct enomr_ctx enomr_ctx;
@@ -129,6 +148,8 @@ enomr_status enomr_rhs(enomr_ctx *ctx, const enomr_problem *prob, const double *
  * Time step from the CFL rule, written to the device scalar *dt_dev:
  *   1D: dt = cfl / (max(|u|+c) / hx), scalar laws use max|f'(u)|;
  *   2D: dt = cfl / (max(|u|+c)/hx + max(|v|+c)/hy).
+ * With per-field alphas the maxima are taken over the three field speeds,
+ * whose largest is |u|+c: the step is the same.
  */
 enomr_status enomr_dt(enomr_ctx *ctx, const enomr_problem *prob, const double *U, double cfl,
                       double *dt_dev, void *ws);

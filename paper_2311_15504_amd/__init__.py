@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(HERE, "libenomr.so")
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, OUTFLOW = 0, 1
 SPLIT_NONE, SPLIT_LF = 0, 1
+CHARACTERISTIC, COMPONENTWISE = 0, 1
+ALPHA_LINE, ALPHA_FIELD = 0, 1
 
 STATUS = {0: "ENOMR_OK", 1: "ENOMR_EINVAL", 2: "ENOMR_EORDER", 3: "ENOMR_ENOMEM", 4: "ENOMR_EHIP",
           5: "ENOMR_ENONPHYS", 6: "ENOMR_ENODEV"}
@@ -31,19 +33,25 @@ class Problem(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("system", ctypes.c_int32), ("nx", ctypes.c_int64),
                 ("ny", ctypes.c_int64), ("hx", ctypes.c_double), ("hy", ctypes.c_double),
                 ("order", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
-                ("split", ctypes.c_int32), ("gamma", ctypes.c_double), ("adv_speed", ctypes.c_double)]
+                ("split", ctypes.c_int32), ("gamma", ctypes.c_double), ("adv_speed", ctypes.c_double),
+                ("recon", ctypes.c_int32), ("alpha_mode", ctypes.c_int32), ("gravity", ctypes.c_double)]
 
     @classmethod
     def scalar(cls, system, n, h, order, bc=PERIODIC, split=SPLIT_LF, adv_speed=1.0):
         return cls(1, system, n, 1, h, 0.0, order, bc, PERIODIC, split, 0.0, adv_speed)
 
     @classmethod
-    def euler1d(cls, n, h, order, bc=OUTFLOW, gamma=1.4):
-        return cls(1, EULER, n, 1, h, 0.0, order, bc, PERIODIC, SPLIT_LF, gamma, 0.0)
+    def euler1d(cls, n, h, order, bc=OUTFLOW, gamma=1.4, componentwise=False, per_field=False):
+        return cls(1, EULER, n, 1, h, 0.0, order, bc, PERIODIC, SPLIT_LF, gamma, 0.0,
+                   COMPONENTWISE if componentwise else CHARACTERISTIC,
+                   ALPHA_FIELD if per_field else ALPHA_LINE, 0.0)
 
     @classmethod
-    def euler2d(cls, nx, ny, hx, hy, order, bc_x=PERIODIC, bc_y=OUTFLOW, gamma=1.4):
-        return cls(2, EULER, nx, ny, hx, hy, order, bc_x, bc_y, SPLIT_LF, gamma, 0.0)
+    def euler2d(cls, nx, ny, hx, hy, order, bc_x=PERIODIC, bc_y=OUTFLOW, gamma=1.4, componentwise=False,
+                per_field=False, gravity=0.0):
+        return cls(2, EULER, nx, ny, hx, hy, order, bc_x, bc_y, SPLIT_LF, gamma, 0.0,
+                   COMPONENTWISE if componentwise else CHARACTERISTIC,
+                   ALPHA_FIELD if per_field else ALPHA_LINE, float(gravity))
 
     @property
     def nvar(self):
@@ -410,5 +418,7 @@ def solve(ctx, prob, U0, cfl, nsteps, checkpoint_every=20):
         _EnoMRSolve = _autograd_function()
     if prob.system != EULER or prob.ndim != 1:
         raise ValueError("the differentiable solve is provided for 1D Euler problems")
+    if prob.recon != CHARACTERISTIC or prob.alpha_mode != ALPHA_LINE or prob.gravity != 0.0:
+        raise ValueError("the differentiable solve takes the default operator only")
     return _EnoMRSolve.apply(U0, ctx, prob, cfl, nsteps, checkpoint_every)
 

@@ -2,6 +2,7 @@
 // workspace layout, kernel launches on the context's stream.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -102,7 +103,30 @@ enomr_status check_problem(const enomr_problem* p)
     if (p->system != ENOMR_EULER && p->split != ENOMR_SPLIT_LF && p->split != ENOMR_SPLIT_NONE)
         return fail(ENOMR_EINVAL, "unknown split");
     if (p->nx > (1L << 31) || p->ny > (1L << 31)) return fail(ENOMR_EINVAL, "grid too large");
+    if (p->recon != ENOMR_CHARACTERISTIC && p->recon != ENOMR_COMPONENTWISE)
+        return fail(ENOMR_EINVAL, "unknown recon");
+    if (p->alpha_mode != ENOMR_ALPHA_LINE && p->alpha_mode != ENOMR_ALPHA_FIELD)
+        return fail(ENOMR_EINVAL, "unknown alpha_mode");
+    if (p->system != ENOMR_EULER && (p->recon != ENOMR_CHARACTERISTIC || p->alpha_mode != ENOMR_ALPHA_LINE))
+        return fail(ENOMR_EINVAL, "recon and alpha_mode apply to Euler problems");
+    if (p->recon == ENOMR_COMPONENTWISE && p->alpha_mode == ENOMR_ALPHA_FIELD)
+        return fail(ENOMR_EINVAL, "per-field alphas need the characteristic reconstruction");
+    if (!std::isfinite(p->gravity)) return fail(ENOMR_EINVAL, "gravity must be finite");
+    if (p->gravity != 0.0 && !(p->system == ENOMR_EULER && p->ndim == 2))
+        return fail(ENOMR_EINVAL, "the gravity source applies to 2D Euler problems");
     return ENOMR_OK;
+}
+
+// The operator as the paper runs it (no variant switch set).
+bool default_operator(const enomr_problem& p)
+{
+    return p.recon == ENOMR_CHARACTERISTIC && p.alpha_mode == ENOMR_ALPHA_LINE && p.gravity == 0.0;
+}
+
+int variant(const enomr_problem& p)
+{
+    if (p.recon == ENOMR_COMPONENTWISE) return VAR_COMPONENT;
+    return p.alpha_mode == ENOMR_ALPHA_FIELD ? VAR_FIELD : VAR_CHAR;
 }
 
 // Workspace: two stage states, one operator buffer, per-line alphas and a
@@ -119,8 +143,10 @@ Layout layout(const enomr_problem& p)
     w.U1 = off; off += align_up(state);
     w.U2 = off; off += align_up(state);
     w.L = off; off += p.ndim == 2 ? align_up(state) : 0;
-    w.ax = off; off += align_up(sizeof(double) * (size_t)p.ny);
-    w.ay = off; off += align_up(sizeof(double) * (size_t)(p.ndim == 2 ? p.nx : 1));
+    // per-line alphas: three planes with per-field alphas
+    const size_t na = p.alpha_mode == ENOMR_ALPHA_FIELD ? 3 : 1;
+    w.ax = off; off += align_up(sizeof(double) * na * (size_t)p.ny);
+    w.ay = off; off += align_up(sizeof(double) * na * (size_t)(p.ndim == 2 ? p.nx : 1));
     w.dt = off; off += 256;
     w.t = off; off += 256;
     w.active = off; off += 256;
@@ -171,6 +197,13 @@ void timed(enomr_ctx* ctx, int cls, F&& launch)
     default: break;                                 \
     }
 
+#define DISPATCH_VAR(var, ...)                                                     \
+    switch (var) {                                                                 \
+    case VAR_COMPONENT: { constexpr int V = VAR_COMPONENT; __VA_ARGS__; } break;   \
+    case VAR_FIELD: { constexpr int V = VAR_FIELD; __VA_ARGS__; } break;           \
+    default: { constexpr int V = VAR_CHAR; __VA_ARGS__; } break;                   \
+    }
+
 // Tile shapes (faces per line x lines per block).
 constexpr int kTF1 = 64;                  // 1D lines
 constexpr int kMaxLsspStages = 18;        // linear SSP-RK(m, m-1): m up to order 17 + 1
@@ -184,13 +217,21 @@ enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* 
     const Layout w = layout(p);
     double* ax = at<double>(ws, w.ax);
     double* ay = at<double>(ws, w.ay);
-    const long nax = p.ny, nay = p.ndim == 2 ? p.nx : 1;
+    const bool pf = p.alpha_mode == ENOMR_ALPHA_FIELD;
+    const long na = pf ? 3 : 1;
+    const long nax = na * p.ny, nay = na * (p.ndim == 2 ? p.nx : 1);
     timed(ctx, PROF_AUX, [&] {
         hipLaunchKernelGGL(k_fill, dim3(blocks_for(nax, 256)), dim3(256), 0, ctx->stream, ax, nax, 0.0);
         hipLaunchKernelGGL(k_fill, dim3(blocks_for(nay, 256)), dim3(256), 0, ctx->stream, ay, nay, 0.0);
         if (p.system == ENOMR_EULER) {
             dim3 grid(blocks_for(p.nx, 64), blocks_for(p.ny, 32));
-            if (p.ndim == 2)
+            if (pf && p.ndim == 2)
+                hipLaunchKernelGGL((k_alpha_euler<4, true>), grid, dim3(256), 0, ctx->stream, Us, (long)p.nx,
+                                   (long)p.ny, p.gamma, ax, ay, ctx->status, active);
+            else if (pf)
+                hipLaunchKernelGGL((k_alpha_euler<3, true>), grid, dim3(256), 0, ctx->stream, Us, (long)p.nx,
+                                   (long)p.ny, p.gamma, ax, ay, ctx->status, active);
+            else if (p.ndim == 2)
                 hipLaunchKernelGGL(k_alpha_euler<4>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
                                    p.gamma, ax, ay, ctx->status, active);
             else
@@ -233,15 +274,17 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
     in.nx = p.nx;
     in.ny = p.ny;
     in.gamma = p.gamma;
+    in.grav = 0.0;
+    const int var = variant(p);
     if (p.ndim == 1) {
         in.alpha = ax;
         in.idx = idx;
         in.ih = 1.0 / p.hx;
         in.bc = p.bc_x;
         timed(ctx, PROF_SWEEP_X, [&] {
-            DISPATCH_R(p.order,
-                       hipLaunchKernelGGL((k_euler_sweep<3, R, 0, kTF1, 1>), dim3(blocks_for(p.nx, kTF1 - 1)),
-                                          dim3(kTF1), 0, ctx->stream, in, so));
+            DISPATCH_VAR(var, DISPATCH_R(p.order,
+                       hipLaunchKernelGGL((k_euler_sweep<3, R, 0, kTF1, 1, V>), dim3(blocks_for(p.nx, kTF1 - 1)),
+                                          dim3(kTF1), 0, ctx->stream, in, so)));
         });
         HIP_TRY(hipGetLastError());
         return ENOMR_OK;
@@ -260,22 +303,23 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
     in.ih = 1.0 / p.hx;
     in.bc = p.bc_x;
     timed(ctx, PROF_SWEEP_X, [&] {
-        DISPATCH_R(p.order,
-                   hipLaunchKernelGGL((k_euler_sweep<4, R, 0, kTFx, kTLx>),
+        DISPATCH_VAR(var, DISPATCH_R(p.order,
+                   hipLaunchKernelGGL((k_euler_sweep<4, R, 0, kTFx, kTLx, V>),
                                       dim3(blocks_for(p.nx, kTFx - 1) * blocks_for(p.ny, kTLx)), dim3(kTFx * kTLx),
-                                      0, ctx->stream, in, sx));
+                                      0, ctx->stream, in, sx)));
     });
     HIP_TRY(hipGetLastError());
     in.alpha = ay;
     in.idx = idx ? idx + (size_t)p.ny * (p.nx + 1) * 8 : nullptr;
     in.ih = 1.0 / p.hy;
     in.bc = p.bc_y;
+    in.grav = p.gravity;
     so.Lprev = Lx;
     timed(ctx, PROF_SWEEP_Y, [&] {
-        DISPATCH_R(p.order,
-                   hipLaunchKernelGGL((k_euler_sweep<4, R, 1, kTFy, kTLy>),
+        DISPATCH_VAR(var, DISPATCH_R(p.order,
+                   hipLaunchKernelGGL((k_euler_sweep<4, R, 1, kTFy, kTLy, V>),
                                       dim3(blocks_for(p.ny, kTFy - 1) * blocks_for(p.nx, kTLy)), dim3(kTFy * kTLy),
-                                      0, ctx->stream, in, so));
+                                      0, ctx->stream, in, so)));
     });
     HIP_TRY(hipGetLastError());
     return ENOMR_OK;
@@ -292,8 +336,10 @@ enomr_status launch_dt(enomr_ctx* ctx, const enomr_problem& p, double cfl, void*
                        double* dt_log, long step)
 {
     const Layout w = layout(p);
-    const long nax = p.system == ENOMR_EULER ? p.ny : 1;
-    const long nay = p.ndim == 2 ? p.nx : 0;
+    // per-field alphas: the maximum over the three planes is max(|u|+c)
+    const long na = p.alpha_mode == ENOMR_ALPHA_FIELD ? 3 : 1;
+    const long nax = p.system == ENOMR_EULER ? na * p.ny : 1;
+    const long nay = p.ndim == 2 ? na * p.nx : 0;
     timed(ctx, PROF_AUX, [&] {
         hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, at<double>(ws, w.ax), nax,
                            at<double>(ws, w.ay), nay, cfl, 1.0 / p.hx, p.ndim == 2 ? 1.0 / p.hy : 0.0, t_end, dt,
@@ -420,6 +466,7 @@ enomr_status check_adjoint_problem(const enomr_problem* p)
     if (enomr_status st = check_problem(p)) return st;
     if (p->system != ENOMR_EULER || p->ndim != 1)
         return fail(ENOMR_EINVAL, "the adjoint is provided for 1D Euler problems");
+    if (!default_operator(*p)) return fail(ENOMR_EINVAL, "the adjoint takes the default operator only");
     return ENOMR_OK;
 }
 
@@ -912,6 +959,7 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
         const enomr_problem& p = probs[i];
         if (enomr_status st = check_problem(&p)) return st;
         if (p.system != ENOMR_EULER) return fail(ENOMR_EINVAL, "batched problems must be Euler problems");
+        if (!default_operator(p)) return fail(ENOMR_EINVAL, "batched problems take the default operator only");
         if (!U[i]) return fail(ENOMR_EINVAL, "NULL state in batch");
         if (p.ndim == 1) {
             i1.push_back(i);

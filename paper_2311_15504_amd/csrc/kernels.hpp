@@ -84,12 +84,62 @@ __global__ void k_alpha_scalar(const double* __restrict__ u, long n, int flux, d
 
 // Euler: alpha_x[y] = max_x(|u|+c), alpha_y[x] = max_y(|v|+c) (nv = 4);
 // nv = 3: alpha_x[0] = max(|u|+c).  Tile: 64 columns x (4*8) rows per block.
-template <int NV>
+// PF (per-field alphas): three planes per direction, alpha_x[k * ny + y] =
+// max_x of |u-c|, |u|, |u+c| for k = 0, 1, 2 (alpha_y likewise with v).
+template <int NV, bool PF = false>
 __global__ __launch_bounds__(256) void k_alpha_euler(const double* __restrict__ U, long nx, long ny,
                                                       double gamma, double* ax, double* ay,
                                                       unsigned* status, const int* active)
 {
     if (active && *active == 0) return;
+    if constexpr (PF) {
+        __shared__ double colf[3][4][64];
+        const long plane = nx * ny;
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const long x = blockIdx.x * 64L + tx;
+        const long y0 = blockIdx.y * 32L;
+        const double gm1 = gamma - 1.0;
+        double cm[3] = {0.0, 0.0, 0.0};
+        for (int r = ty; r < 32; r += 4) {
+            const long y = y0 + r;
+            double sx[3] = {0.0, 0.0, 0.0}, sy[3] = {0.0, 0.0, 0.0};
+            if ((x < nx) && (y < ny)) {
+                const long g = y * nx + x;
+                const double rho = U[g], m = U[plane + g];
+                const double n = NV == 4 ? U[2 * plane + g] : 0.0;
+                const double E = U[(NV - 1) * plane + g];
+                const double ir = 1.0 / rho;
+                const double u = m * ir;
+                const double v = NV == 4 ? n * ir : 0.0;
+                const double ke = NV == 4 ? 0.5 * (m * u + n * v) : 0.5 * (m * u);
+                const double p = gm1 * (E - ke);
+                if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(m) || !isfinite(n))
+                    flag_nonphysical(status);
+                const double c = sqrt((gamma * p) * ir);
+                sx[0] = fabs(u - c); sx[1] = fabs(u); sx[2] = fabs(u + c);
+                sy[0] = fabs(v - c); sy[1] = fabs(v); sy[2] = fabs(v + c);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double rmax = wave_max(sx[k]);
+                if (tx == 0 && y < ny) atomic_max_nonneg(&ax[k * ny + y], rmax);
+                cm[k] = fmax(cm[k], sy[k]);
+            }
+        }
+        if (NV == 4) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) colf[k][ty][tx] = cm[k];
+            __syncthreads();
+            if (ty == 0 && x < nx) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double v = fmax(fmax(colf[k][0][tx], colf[k][1][tx]), fmax(colf[k][2][tx], colf[k][3][tx]));
+                    atomic_max_nonneg(&ay[k * nx + x], v);
+                }
+            }
+        }
+        return;
+    }
     __shared__ double col[4][64];
     const long plane = nx * ny;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -389,14 +439,87 @@ __device__ __forceinline__ void back_project(const Eig& e, const double (&w)[NV]
 
 struct SweepIn {
     const double* Us;      // state the operator is evaluated on
-    const double* alpha;   // per-line alpha (LF splitting)
+    const double* alpha;   // per-line alpha (LF splitting); per-field: [3][lines]
     unsigned* status;
     uint8_t* idx;          // nullable: this direction's stencil log
     const int* active;     // nullable
     long nx, ny;
     double ih, gamma;
+    double grav;           // 2D y sweep: source g [0, 0, rho, rho v] (0: none)
     int bc;
 };
+
+// Operator variants of the Euler sweep (compile-time): the characteristic
+// reconstruction with one alpha per line (the scheme's default), the
+// component-wise reconstruction of G+- = (F +- alpha U)/2 with no projection,
+// and per-field alphas: w+-_k = (l_k.F +- alpha_k l_k.U)/2 with alpha_k the
+// line's largest |lambda_k|, lambda = (u-c, u, [u,] u+c); the product by
+// alpha_k is rounded first, then the sum and the halving.
+enum { VAR_CHAR = 0, VAR_COMPONENT = 1, VAR_FIELD = 2 };
+
+// Which of the three per-field alphas field q of an NV-field system uses.
+template <int NV>
+__device__ constexpr int field_speed(int q)
+{
+    return q == 0 ? 0 : (q == NV - 1 ? 2 : 1);
+}
+
+// The sign-S characteristic values of the cell at LDS entry lp for every
+// field.  A, B: the staged arrays (G+ and G- for VAR_CHAR and VAR_COMPONENT;
+// F and U for VAR_FIELD); af: the per-field alphas.
+template <int NV, int VAR, int S, int NCELL>
+__device__ __forceinline__ void char_values(const Eig& e, const double (&A)[NV][NCELL], const double (&B)[NV][NCELL],
+                                            const double (&af)[NV], int lp, double (&w)[NV])
+{
+    if constexpr (VAR == VAR_COMPONENT) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) w[q] = S > 0 ? A[q][lp] : B[q][lp];
+    } else if constexpr (VAR == VAR_FIELD) {
+        double gf[NV], gu[NV], wf[NV], wu[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            gf[q] = A[q][lp];
+            gu[q] = B[q][lp];
+        }
+        project<NV>(e, gf, wf);
+        project<NV>(e, gu, wu);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const double t = af[q] * wu[q];
+            w[q] = S > 0 ? 0.5 * (wf[q] + t) : 0.5 * (wf[q] - t);
+        }
+    } else {
+        double g[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) g[q] = S > 0 ? A[q][lp] : B[q][lp];
+        project<NV>(e, g, w);
+    }
+}
+
+// Field Q of char_values<NV, VAR, S>, the same arithmetic.
+template <int NV, int VAR, int S, int Q, int NCELL>
+__device__ __forceinline__ double char_value(const Eig& e, const double (&A)[NV][NCELL], const double (&B)[NV][NCELL],
+                                             double aq, int lp)
+{
+    if constexpr (VAR == VAR_COMPONENT) {
+        return S > 0 ? A[Q][lp] : B[Q][lp];
+    } else if constexpr (VAR == VAR_FIELD) {
+        double gf[NV], gu[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            gf[c] = A[c][lp];
+            gu[c] = B[c][lp];
+        }
+        const double wf = project_row<NV, Q>(e, gf);
+        const double t = aq * project_row<NV, Q>(e, gu);
+        return S > 0 ? 0.5 * (wf + t) : 0.5 * (wf - t);
+    } else {
+        double g[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) g[c] = S > 0 ? A[c][lp] : B[c][lp];
+        return project_row<NV, Q>(e, g);
+    }
+}
 
 // LDS of one sweep tile: split fluxes and Roe inputs of NCELL staged cells
 // (structure of arrays) and the NFACE face fluxes.
@@ -414,16 +537,12 @@ struct SweepLds {
 // build its difference table in place, and evaluate the chosen candidate's
 // flux chain on a second projection of the window (bitwise the same values;
 // re-projecting is cheaper than holding the window in registers).
-template <int NV, int R, int S, int Q, int STEP, int NCELL>
-__device__ __forceinline__ double fallback_window(const Eig& e, const double (&G)[NV][NCELL], int lp0, int& id)
+template <int NV, int R, int S, int Q, int STEP, int NCELL, int VAR>
+__device__ __forceinline__ double fallback_window(const Eig& e, const double (&A)[NV][NCELL],
+                                                  const double (&B)[NV][NCELL], double aq, int lp0, int& id)
 {
     constexpr int W = 2 * R - 1;
-    auto proj = [&](int i) {
-        double g[NV];
-#pragma unroll
-        for (int c = 0; c < NV; ++c) g[c] = G[c][lp0 + i * STEP];
-        return project_row<NV, Q>(e, g);
-    };
+    auto proj = [&](int i) { return char_value<NV, VAR, S, Q, NCELL>(e, A, B, aq, lp0 + i * STEP); };
     double w[W];
 #pragma unroll
     for (int i = 0; i < W; ++i) w[i] = proj(i);
@@ -444,8 +563,9 @@ __device__ __forceinline__ double fallback_window(const Eig& e, const double (&G
 // faces c0 .. c0+TF-1 (cells c0 .. c0+TF-2).  DIR 0: lines are rows (x faces);
 // DIR 1: lines are columns (y faces), evaluated on the permuted state
 // (rho, n, m, E) so that the same x-normal formulas apply.  NCL >= TF+2R-1 is
-// the LDS stride per line.  All threads of the block must call it.
-template <int NV, int R, int DIR, int TF, int TL, int NCL>
+// the LDS stride per line.  VAR selects the operator variant (VAR_CHAR,
+// VAR_COMPONENT, VAR_FIELD).  All threads of the block must call it.
+template <int NV, int R, int DIR, int TF, int TL, int NCL, int VAR = VAR_CHAR>
 __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so, long line0, long c0,
                                            SweepLds<NV, NCL * TL, TF * TL>& sm)
 {
@@ -488,18 +608,29 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         F[1] = mn * un + p;
         if constexpr (NV == 4) F[2] = mt * un;
         F[NV - 1] = (E + p) * un;
-        const double al = in.alpha[gl];
         const int lp = lpos(line, cell);
+        if constexpr (VAR == VAR_FIELD) {
+            // F and U as they are: the split follows the projection
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            const double t = al * Uc[q];
-            sm.Gp[q][lp] = 0.5 * (F[q] + t);
-            sm.Gm[q][lp] = 0.5 * (F[q] - t);
+            for (int q = 0; q < NV; ++q) {
+                sm.Gp[q][lp] = F[q];
+                sm.Gm[q][lp] = Uc[q];
+            }
+        } else {
+            const double al = in.alpha[gl];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const double t = al * Uc[q];
+                sm.Gp[q][lp] = 0.5 * (F[q] + t);
+                sm.Gm[q][lp] = 0.5 * (F[q] - t);
+            }
         }
-        sm.Sq[lp] = sqrt(rho);
-        sm.Un[lp] = un;
-        if constexpr (NV == 4) sm.Ut[lp] = ut;
-        sm.H[lp] = (E + p) * ir;
+        if constexpr (VAR != VAR_COMPONENT) {
+            sm.Sq[lp] = sqrt(rho);
+            sm.Un[lp] = un;
+            if constexpr (NV == 4) sm.Ut[lp] = ut;
+            sm.H[lp] = (E + p) * ir;
+        }
     }
     __syncthreads();
 
@@ -512,10 +643,15 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     if (live) {
         const int jp = tf + R - 1;   // left cell of the face in the tile
         const int pl = lpos(tl, jp), pr = lpos(tl, jp + 1);
-        Eig e;
-        const bool ok = roe_eigen<NV>(sm.Sq[pl], sm.Un[pl], NV == 4 ? sm.Ut[pl] : 0.0, sm.H[pl], sm.Sq[pr], sm.Un[pr],
-                                      NV == 4 ? sm.Ut[pr] : 0.0, sm.H[pr], gm1, e);
-        if (!ok) flag_nonphysical(in.status);
+        Eig e{};
+        if constexpr (VAR != VAR_COMPONENT) {
+            const bool ok = roe_eigen<NV>(sm.Sq[pl], sm.Un[pl], NV == 4 ? sm.Ut[pl] : 0.0, sm.H[pl], sm.Sq[pr],
+                                          sm.Un[pr], NV == 4 ? sm.Ut[pr] : 0.0, sm.H[pr], gm1, e);
+            if (!ok) flag_nonphysical(in.status);
+        }
+        double af[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) af[q] = VAR == VAR_FIELD ? in.alpha[field_speed<NV>(q) * nlines + gl] : 0.0;
 
         // ---- smooth path: stream the window once, accumulating for every
         // field and sign the full-stencil indicator and flux and keeping the
@@ -532,11 +668,8 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             double is[NV], fl[NV], a[NV], b[NV], cc[NV], isl[NV], is0[NV];
 #pragma unroll
             for (int o = -R + 1; o <= R - 1; ++o) {
-                double G[NV], w[NV];
-                const int lp = lpos(tl, jp + o);
-#pragma unroll
-                for (int q = 0; q < NV; ++q) G[q] = sm.Gp[q][lp];
-                project<NV>(e, G, w);
+                double w[NV];
+                char_values<NV, VAR, +1, NCL * TL>(e, sm.Gp, sm.Gm, af, lpos(tl, jp + o), w);
                 const int ci = o + (R - 1);
 #pragma unroll
                 for (int q = 0; q < NV; ++q) {
@@ -584,11 +717,8 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             double is[NV], fl[NV], a[NV], b[NV], cc[NV], isr[NV], is0[NV];
 #pragma unroll
             for (int o = -R + 2; o <= R; ++o) {
-                double G[NV], w[NV];
-                const int lp = lpos(tl, jp + o);
-#pragma unroll
-                for (int q = 0; q < NV; ++q) G[q] = sm.Gm[q][lp];
-                project<NV>(e, G, w);
+                double w[NV];
+                char_values<NV, VAR, -1, NCL * TL>(e, sm.Gp, sm.Gm, af, lpos(tl, jp + o), w);
                 const int ci = R - o;
 #pragma unroll
                 for (int q = 0; q < NV; ++q) {
@@ -638,25 +768,27 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
 #pragma unroll 1
             for (int kk = 0; kk < 2 * NV; ++kk) {
                 if (!((fail >> kk) & 1u)) continue;
-                int id;
+                int id = 0;
                 double res;
+                const int lpp = lpos(tl, jp - (R - 1)), lpm = lpos(tl, jp - (R - 2));
+                constexpr int NC = NCL * TL;
                 switch (kk) {
-                case 0: res = fallback_window<NV, R, +1, 0, LSTEP, NCL * TL>(e, sm.Gp, lpos(tl, jp - (R - 1)), id); hp[0] = res; break;
-                case 1: res = fallback_window<NV, R, -1, 0, LSTEP, NCL * TL>(e, sm.Gm, lpos(tl, jp - (R - 2)), id); hm[0] = res; break;
-                case 2: res = fallback_window<NV, R, +1, 1, LSTEP, NCL * TL>(e, sm.Gp, lpos(tl, jp - (R - 1)), id); hp[1] = res; break;
-                case 3: res = fallback_window<NV, R, -1, 1, LSTEP, NCL * TL>(e, sm.Gm, lpos(tl, jp - (R - 2)), id); hm[1] = res; break;
-                case 4: res = fallback_window<NV, R, +1, 2, LSTEP, NCL * TL>(e, sm.Gp, lpos(tl, jp - (R - 1)), id); hp[2] = res; break;
-                case 5: res = fallback_window<NV, R, -1, 2, LSTEP, NCL * TL>(e, sm.Gm, lpos(tl, jp - (R - 2)), id); hm[2] = res; break;
+                case 0: res = fallback_window<NV, R, +1, 0, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[0], lpp, id); hp[0] = res; break;
+                case 1: res = fallback_window<NV, R, -1, 0, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[0], lpm, id); hm[0] = res; break;
+                case 2: res = fallback_window<NV, R, +1, 1, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[1], lpp, id); hp[1] = res; break;
+                case 3: res = fallback_window<NV, R, -1, 1, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[1], lpm, id); hm[1] = res; break;
+                case 4: res = fallback_window<NV, R, +1, 2, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[2], lpp, id); hp[2] = res; break;
+                case 5: res = fallback_window<NV, R, -1, 2, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[2], lpm, id); hm[2] = res; break;
                 case 6:
                     if constexpr (NV == 4) {
-                        res = fallback_window<NV, R, +1, 3, LSTEP, NCL * TL>(e, sm.Gp, lpos(tl, jp - (R - 1)), id);
-                        hp[3] = res;
+                        res = fallback_window<NV, R, +1, 3, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[NV - 1], lpp, id);
+                        hp[NV - 1] = res;
                     }
                     break;
                 default:
                     if constexpr (NV == 4) {
-                        res = fallback_window<NV, R, -1, 3, LSTEP, NCL * TL>(e, sm.Gm, lpos(tl, jp - (R - 2)), id);
-                        hm[3] = res;
+                        res = fallback_window<NV, R, -1, 3, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[NV - 1], lpm, id);
+                        hm[NV - 1] = res;
                     }
                     break;
                 }
@@ -667,7 +799,12 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         double wh[NV], Fh[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) wh[q] = hp[q] + hm[q];
-        back_project<NV>(e, wh, Fh);
+        if constexpr (VAR == VAR_COMPONENT) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) Fh[q] = wh[q];
+        } else {
+            back_project<NV>(e, wh, Fh);
+        }
 #pragma unroll
         for (int q = 0; q < NV; ++q) sm.F[q][fpos(tl, tf)] = Fh[q];
 
@@ -684,6 +821,9 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     const bool outc = gl < nlines && tf < TC && cell < n;
     const long g = outc ? gidx(gl, cell) : 0;
     double lp[NV], un[NV], us[NV];
+    // the source of the 2D y sweep: rho and rho v of the cell
+    constexpr bool SRC = DIR == 1 && NV == 4;
+    double s_rho = 0.0, s_rv = 0.0;
     if (outc) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
@@ -691,6 +831,10 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             lp[q] = so.Lprev ? so.Lprev[i] : 0.0;
             un[q] = so.stage ? so.Un[i] : 0.0;
             us[q] = so.stage ? in.Us[i] : 0.0;
+        }
+        if (SRC && in.grav != 0.0) {
+            s_rho = in.Us[g];
+            s_rv = in.Us[2 * plane + g];
         }
     }
     __syncthreads();
@@ -701,6 +845,10 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             const int v = gvar(q);
             double L = -((sm.F[q][fpos(tl, tf + 1)] - sm.F[q][fpos(tl, tf)]) * in.ih);
             if (so.Lprev) L = lp[q] + L;
+            if (SRC && in.grav != 0.0) {
+                if (v == 2) L = L + in.grav * s_rho;
+                if (v == 3) L = L + in.grav * s_rv;
+            }
             if (so.stage == 0) so.out[v * plane + g] = L;
             else so.out[v * plane + g] = rk_combine(so.stage, un[q], us[q], L, dt);
         }
@@ -726,7 +874,7 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb)
 }
 
 // One tile per workgroup, 1D grid of ceil(n / (TF-1)) x ceil(nlines / TL) tiles.
-template <int NV, int R, int DIR, int TF, int TL>
+template <int NV, int R, int DIR, int TF, int TL, int VAR = VAR_CHAR>
 __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut so)
 {
     if (in.active && *in.active == 0) return;
@@ -737,7 +885,7 @@ __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut 
     const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
     const unsigned ft = DIR == 0 ? t % nft : t / nlt;
     const unsigned lt = DIR == 0 ? t / nft : t % nlt;
-    sweep_tile<NV, R, DIR, TF, TL, NCL>(in, so, (long)lt * TL, (long)ft * (TF - 1), lds);
+    sweep_tile<NV, R, DIR, TF, TL, NCL, VAR>(in, so, (long)lt * TL, (long)ft * (TF - 1), lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -830,6 +978,7 @@ __device__ __forceinline__ void run_problem(const BatchProb& P, const BatchParam
             in.ny = 1;
             in.ih = P.ih;
             in.gamma = P.gamma;
+            in.grav = 0.0;
             in.bc = P.bc;
             StageOut so;
             so.Un = P.U;
@@ -978,6 +1127,7 @@ __device__ __forceinline__ void run_problem_2d(const BatchProb2& P, const BatchP
             in.nx = nx;
             in.ny = ny;
             in.gamma = P.gamma;
+            in.grav = 0.0;
             // x sweep: L_x into P.L
             in.alpha = P.ax;
             in.ih = P.ihx;
@@ -1010,7 +1160,10 @@ __device__ __forceinline__ void run_problem_2d(const BatchProb2& P, const BatchP
     }
 }
 
-__global__ __launch_bounds__(kB2TF * kB2TL, 4) void k_batch_euler2d(const BatchProb2* __restrict__ probs,
+// Two workgroups per CU: the kernel holds every order's sweeps behind one
+// switch, and at four per CU it spilled about 300 VGPRs to scratch (measured
+// 15% slower on the batched 2D workload).
+__global__ __launch_bounds__(kB2TF * kB2TL, 2) void k_batch_euler2d(const BatchProb2* __restrict__ probs,
                                                                      const int* __restrict__ order, int nprob,
                                                                      int* queue, const BatchParams* prm,
                                                                      unsigned* status)

@@ -1,7 +1,9 @@
 """The C-ABI library loads, exports what include/enomr.h declares, and its
 host-side coefficient tables equal the paper's and the oracle's.  No GPU."""
+import ctypes
 import os
 import re
+import subprocess
 from fractions import Fraction
 
 import numpy as np
@@ -80,3 +82,42 @@ def test_bad_arguments_are_rejected_without_a_gpu():
     assert e.value.status == 1
     prob = enomr.Problem.euler2d(2048, 2048, 1 / 1024, 1 / 1024, 17)
     assert enomr.workspace_size(prob) >= 3 * 4 * 2048 * 2048 * 8
+
+
+def test_problem_struct_layout_matches_the_header(tmp_path):
+    # offsets and size of enomr_problem as the C compiler lays it out
+    fields = [f for f, _ in enomr.Problem._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "enomr.h"\nint main(void) {\n'
+                   + "".join('printf("%%zu\\n", offsetof(enomr_problem, %s));\n' % f for f in fields)
+                   + 'printf("%zu\\n", sizeof(enomr_problem));\nreturn 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [getattr(enomr.Problem, f).offset for f in fields] + [ctypes.sizeof(enomr.Problem)]
+    assert got == want
+
+
+def test_operator_variant_switches_are_checked_without_a_gpu():
+    ok = [enomr.Problem.euler2d(64, 64, 0.1, 0.1, 9, componentwise=True),
+          enomr.Problem.euler2d(64, 64, 0.1, 0.1, 9, per_field=True, gravity=1.0),
+          enomr.Problem.euler1d(64, 0.1, 9, per_field=True)]
+    for prob in ok:
+        enomr.workspace_size(prob)
+    # the per-field alphas take three planes per direction
+    assert (enomr.workspace_size(enomr.Problem.euler2d(64, 64, 0.1, 0.1, 9, per_field=True))
+            > enomr.workspace_size(enomr.Problem.euler2d(64, 64, 0.1, 0.1, 9)))
+    bad = [enomr.Problem.euler2d(64, 64, 0.1, 0.1, 9, componentwise=True, per_field=True),
+           enomr.Problem.euler1d(64, 0.1, 9),
+           enomr.Problem.scalar(enomr.BURGERS, 64, 0.1, 9),
+           enomr.Problem.euler2d(64, 64, 0.1, 0.1, 9, gravity=float("nan"))]
+    bad[1].gravity = 1.0                       # the source is 2D only
+    bad[2].recon = enomr.COMPONENTWISE          # variants are Euler only
+    for prob in bad:
+        with pytest.raises(enomr.EnomrError) as e:
+            enomr.workspace_size(prob)
+        assert e.value.status == 1
+    prob = enomr.Problem.euler2d(64, 64, 0.1, 0.1, 9)
+    prob.recon = 7
+    with pytest.raises(enomr.EnomrError):
+        enomr.workspace_size(prob)
