@@ -313,6 +313,56 @@ def run_batched_2d(args):
             "speedup_vs_per_problem": value / value_pp, "sample_bitwise_equal": bool(same)}
 
 
+SCALAR_BYTES_PER_CELL_STAGE = 64.0 / 3.0   # read U^(s), read U^n (stages 2, 3), write U^(s+1)
+
+
+def run_scalar(args):
+    """Scalar path: 1D linear advection with the LF split, the seeded sines +
+    step data on [-1, 1] periodic, n = 2^27 nodes, SSP-RK3 at CFL 0.5, orders
+    5 and 17 by default.  HBM-bound: the roofline is the compulsory state traffic per
+    cell-update (21.3 B averaged over the three stages) against 8 TB/s."""
+    import torch
+
+    import paper_2311_15504_amd as enomr
+    import workloads
+
+    n = args.scalar_n
+    steps = args.scalar_steps
+    _, h, u0 = workloads.advection_sines_step(args.seed, n)
+    out = {"workload": "1D advection, LF split, seeded sines + step, n = %d, periodic, %d SSP-RK3 steps at CFL 0.5"
+                       % (n, steps)}
+    ctx = enomr.Context(0)
+    U0 = torch.from_numpy(u0[None]).cuda()
+    for order in [int(o) for o in args.scalar_orders.split(",")]:
+        prob = enomr.Problem.scalar(enomr.ADVECTION, n, h, order, enomr.PERIODIC, enomr.SPLIT_LF, 1.0)
+        U = U0.clone()
+        ctx.workspace(prob)
+        ctx.advance(prob, U, 0.5, 1)
+        ctx.check()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        ctx.profile_start()
+        e0.record(stream)
+        ctx.advance(prob, U, 0.5, steps)
+        e1.record(stream)
+        prof = ctx.profile_stop()
+        torch.cuda.synchronize()
+        ctx.check()
+        ms = e0.elapsed_time(e1)
+        value = n * 3 * steps / (ms * 1e-3)
+        sweep_ms, sweeps = prof["sweep_x"]
+        gbs = SCALAR_BYTES_PER_CELL_STAGE * n * sweeps / (sweep_ms * 1e-3) / 1e9
+        kern = "k_scalar_sweep_dpp (windows shared lane to lane)" if order == 5 else "k_scalar_sweep (LDS windows)"
+        out["order%d" % order] = {"kernel": kern, "value": value, "unit": "cell-updates/s", "ms_per_step": ms / steps,
+                                  "sweep_us": 1e3 * sweep_ms / sweeps,
+                                  "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                                               "frac": gbs / 8000.0}}
+    ctx.close()
+    return out
+
+
 def run_adjoint(args):
     """Adjoint workload: 1D Euler, N = 8192, order 9, smooth periodic data, 400
     SSP-RK3 steps checkpointed every 20; loss = h sum (rho_T - rho*)^2.
@@ -508,6 +558,10 @@ def main():
     ap.add_argument("--no-batched-2d", action="store_true")
     ap.add_argument("--batch2d-problems", type=int, default=256)
     ap.add_argument("--batch2d-steps", type=int, default=20)
+    ap.add_argument("--no-scalar", action="store_true")
+    ap.add_argument("--scalar-n", type=int, default=1 << 27)
+    ap.add_argument("--scalar-steps", type=int, default=10)
+    ap.add_argument("--scalar-orders", default="5,17")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--no-replay", action="store_true",
@@ -537,6 +591,7 @@ def main():
         out["order13"]["roofline_frac"] = o13["roofline"]["frac"] if o13.get("roofline") else None
     out["batched"] = None if args.no_batched else run_batched(args)
     out["batched_2d"] = None if args.no_batched_2d else run_batched_2d(args)
+    out["scalar"] = None if args.no_scalar else run_scalar(args)
     out["adjoint"] = None if args.no_adjoint else run_adjoint(args)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args)
     if args.calib_copy_mib:

@@ -305,9 +305,10 @@ class Context:
 
 
 class Batch:
-    """Many independent 1D Euler problems advanced by one persistent launch
-    (enomr_batch_*).  `states` are the problems' [3][n] float64 CUDA tensors;
-    they stay bound to the batch and are advanced in place."""
+    """Many independent 1D and 2D Euler problems advanced by persistent
+    launches replayed from one graph (enomr_batch_*).  `states` are the
+    problems' [3][n] or [4][ny][nx] float64 CUDA tensors; they stay bound to
+    the batch and are advanced in place."""
 
     def __init__(self, ctx, problems, states, autotune=True, tile_faces=None):
         """autotune: time the tile widths 64/128/256 and keep the fastest;

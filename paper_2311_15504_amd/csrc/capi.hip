@@ -206,6 +206,12 @@ void timed(enomr_ctx* ctx, int cls, F&& launch)
 
 // Tile shapes (faces per line x lines per block).
 constexpr int kTF1 = 64;                  // 1D lines
+// Scalar laws: windows shared lane to lane (k_scalar_sweep_dpp) or staged in
+// LDS (k_scalar_sweep), per order by measurement on MI355X (1D advection,
+// 2^27 nodes): lane sharing is 14% faster at order 5 and 2% to 44% slower
+// from order 7 up, where its register windows (4 cells per lane) lower the
+// occupancy to 2-4 waves per SIMD.
+constexpr bool scalar_lane_shared(int R) { return R == 3; }
 constexpr int kMaxLsspStages = 18;        // linear SSP-RK(m, m-1): m up to order 17 + 1
 constexpr int kTFx = 64, kTLx = 4;        // 2D x sweep
 constexpr int kTFy = 64, kTLy = 4;        // 2D y sweep
@@ -260,9 +266,17 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
         const int split = p.split == ENOMR_SPLIT_LF ? 1 : 0;
         timed(ctx, PROF_SWEEP_X, [&] {
             DISPATCH_R(p.order,
-                       hipLaunchKernelGGL((k_scalar_sweep<R, kTF1>), dim3(blocks_for(p.nx, kTF1 - 1)), dim3(kTF1),
-                                          0, ctx->stream, Us, (long)p.nx, 1.0 / p.hx, flux, p.adv_speed, split,
-                                          p.bc_x, ax, so, idx, active));
+                       if constexpr (scalar_lane_shared(R)) {
+                           // 64 kScalarKC - 2R cells per wave, four waves per block
+                           const long nw = (long)blocks_for(p.nx, 64 * kScalarKC - 2 * R);
+                           hipLaunchKernelGGL((k_scalar_sweep_dpp<R>), dim3(blocks_for(nw, 4)), dim3(256), 0,
+                                              ctx->stream, Us, (long)p.nx, 1.0 / p.hx, flux, p.adv_speed, split,
+                                              p.bc_x, ax, so, idx, active);
+                       } else {
+                           hipLaunchKernelGGL((k_scalar_sweep<R, kTF1>), dim3(blocks_for(p.nx, kTF1 - 1)),
+                                              dim3(kTF1), 0, ctx->stream, Us, (long)p.nx, 1.0 / p.hx, flux,
+                                              p.adv_speed, split, p.bc_x, ax, so, idx, active);
+                       });
         });
         HIP_TRY(hipGetLastError());
         return ENOMR_OK;

@@ -317,6 +317,150 @@ __global__ __launch_bounds__(TF) void k_scalar_sweep(const double* __restrict__ 
     }
 }
 
+// The same sweep with the window shared lane to lane instead of through LDS.
+// In the component-wise scalar reconstruction neighbouring faces read the
+// same split-flux values.  Each lane loads KC = 4 consecutive cells and keeps
+// the split fluxes of every cell its four faces read in registers: its own
+// cells, and R to the left and R-1 to the right taken from the neighbouring
+// lanes by wavefront shifts (DPP wave_shr:1 / wave_shl:1 move all four values
+// of a lane one lane over: two 32-bit moves per double).  A wave covers
+// 64 KC = 256 cells and reconstructs the 257-2R faces whose 2R-cell windows
+// lie inside it; waves overlap by one face, so every cell's two faces come
+// from the same wave.  Four cells per lane keep four loads in flight per lane
+// and share each lane's registers between four windows.  No LDS, no barrier.
+// The windows hold the same values as the LDS sweep's, so the results are
+// the same bit for bit.  Shifts run with every lane of the wave active
+// (before any branch on the data); lanes whose faces fall outside the wave
+// compute on values they never store.
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    // CTRL 0x130: wave_shl:1 (lane i takes lane i+1); 0x138: wave_shr:1 (lane i
+    // takes lane i-1); the edge lane keeps its own value
+    const int slo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const int shi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)shi << 32) | (unsigned)slo);
+}
+__device__ __forceinline__ double from_right(double v) { return wave_shift<0x130>(v); }
+__device__ __forceinline__ double from_left(double v) { return wave_shift<0x138>(v); }
+
+constexpr int kScalarKC = 4;   // cells per lane of the lane-shared scalar sweep
+
+// The values at lane-relative cells k = LO .. HI (k = 0 .. KC-1 are the lane's
+// own) from the own values v[0 .. KC-1]: out[k - LO].
+template <int LO, int HI>
+__device__ __forceinline__ void gather_neighbours(const double (&v)[kScalarKC], double (&out)[HI - LO + 1])
+{
+    constexpr int KC = kScalarKC;
+    double cur[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        cur[k] = v[k];
+        if (k >= LO && k <= HI) out[k - LO] = v[k];
+    }
+    // to the left: lane l-1's cells are k - KC
+#pragma unroll
+    for (int step = 1; step * KC <= -LO + KC - 1; ++step) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            cur[k] = from_left(cur[k]);
+            const int rel = k - step * KC;
+            if (rel >= LO && rel <= HI) out[rel - LO] = cur[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) cur[k] = v[k];
+    // to the right: lane l+1's cells are k + KC
+#pragma unroll
+    for (int step = 1; step * KC <= HI; ++step) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            cur[k] = from_right(cur[k]);
+            const int rel = k + step * KC;
+            if (rel >= LO && rel <= HI) out[rel - LO] = cur[k];
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_scalar_sweep_dpp(const double* __restrict__ us, long n, double ih,
+                                                          int flux, double a, int split, int bc,
+                                                          const double* alpha, StageOut so, uint8_t* idx,
+                                                          const int* active)
+{
+    if (active && *active == 0) return;
+    constexpr int KC = kScalarKC;
+    constexpr int W = 2 * R - 1;
+    constexpr int CW = 64 * KC - 2 * R;       // cells written per wave (faces per wave - 1)
+    const int lane = threadIdx.x & 63;
+    const long wave = blockIdx.x * 4L + (threadIdx.x >> 6);
+    const long base = wave * CW - R;          // the wave's first cell (wave-local cell 0)
+    const double al = split ? *alpha : 0.0;
+    // own cells base + KC lane + k; the stage's U^n at the same cells
+    double u[KC], gp[KC], gm[KC], un[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) u[k] = us[map_cell(base + KC * lane + k, n, bc)];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const long c = base + KC * lane + k;
+        un[k] = (so.stage && c >= 0 && c < n) ? so.Un[c] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const double f = flux == SYS_ADVECTION ? a * u[k] : 0.5 * u[k] * u[k];
+        if (split) {
+            const double t = al * u[k];
+            gp[k] = 0.5 * (f + t);
+            gm[k] = 0.5 * (f - t);
+        } else {
+            gp[k] = f;
+            gm[k] = 0.0;
+        }
+    }
+    // face j of the lane (between lane-relative cells j-1 and j) reads f^+ at
+    // cells j-R .. j+R-2 and f^- at cells j-R+1 .. j+R-1
+    double P[KC + W - 1], M[KC + W - 1];
+    gather_neighbours<-R, KC + R - 3>(gp, P);
+    gather_neighbours<-R + 1, KC + R - 2>(gm, M);
+    double fh[KC];
+    int ip[KC], im[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        double wp[W], wm[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            wp[i] = P[j + i];
+            wm[i] = M[j + i];
+        }
+        const double hp = recon<R, +1>(wp, ip[j]);
+        double hm = 0.0;
+        im[j] = 0;
+        if (split) hm = recon<R, -1>(wm, im[j]);
+        fh[j] = hp + hm;
+    }
+    const double fnext = from_right(fh[0]);   // the next lane's first face
+    const double ihv = ih;
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        const int F = KC * lane + j;           // wave-local face index
+        const long face = base + F;
+        if (F >= R && F <= 64 * KC - R && face <= n && idx) {
+            idx[2 * face] = (uint8_t)ip[j];
+            idx[2 * face + 1] = (uint8_t)im[j];
+        }
+        const long cell = face;               // between faces F and F+1
+        if (F >= R && F <= 64 * KC - 1 - R && cell < n) {
+            const double right = j + 1 < KC ? fh[j + 1 < KC ? j + 1 : 0] : fnext;
+            double L = -((right - fh[j]) * ihv);
+            if (so.Lprev) L = so.Lprev[cell] + L;
+            if (so.stage == 0) so.out[cell] = L;
+            else so.out[cell] = rk_combine(so.stage, un[j], u[j], L, *so.dt);
+        }
+    }
+}
+
 // Last stage of the linear SSP-RK(m, m-1) step (Sec. 2.3, Eq. lSSPRK):
 // u = sum_{k < m-1} a_k u^(k) + a_{m-1} (u^(m-1) + hdt L), the sum taken in
 // ascending k from zero, each term a product then an add.

@@ -296,3 +296,23 @@ def test_runs_are_deterministic(ctx):
     ctx.advance(prob, B, 0.5, 3)
     ctx.check()
     assert np.array_equal(_host(A), _host(B))
+
+
+@pytest.mark.parametrize("order", [5, 9, 13, 17])
+def test_scalar_operator_many_waves_bitwise(ctx, order):
+    # The scalar sweep shares windows lane to lane: many waves, a ragged last
+    # wave and both boundary kinds, LF-split advection and unsplit Burgers.
+    import paper_2311_15504_amd as enomr
+    n = 20011
+    _, h, u = workloads.advection_sines_step(order + 3, n)
+    for bc in (enomr.PERIODIC, enomr.OUTFLOW):
+        ref, ridx, _ = oracle.scalar_rhs(order, u, h, bc=bc, with_idx=True)
+        got, gidx = ctx.rhs(enomr.Problem.scalar(enomr.ADVECTION, n, h, order, bc), _dev(u[None]), with_idx=True)
+        ctx.check()
+        assert np.array_equal(_host(gidx).reshape(-1, 2), ridx.reshape(-1, 2))
+        assert np.array_equal(_host(got)[0], ref)
+        ub = 1.5 + u                                   # positive: f'(u) = u > 0, no split needed
+        ref = oracle.scalar_rhs(order, ub, h, flux=oracle.BURGERS, split=oracle.SPLIT_NONE, bc=bc)
+        got = ctx.rhs(enomr.Problem.scalar(enomr.BURGERS, n, h, order, bc, enomr.SPLIT_NONE), _dev(ub[None]))
+        ctx.check()
+        assert np.array_equal(_host(got)[0], ref)
