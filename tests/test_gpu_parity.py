@@ -229,8 +229,12 @@ def test_euler2d_run_matches_oracle(ctx):
     ref, dts = oracle.euler2d_run(17, U0, hx, hy, 8, cfl=0.5)
     prob = enomr.Problem.euler2d(nx, ny, hx, hy, 17)
     U = _dev(U0)
-    ctx.advance(prob, U, 0.5, 8)
+    import torch
+    dt_log = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ctx.advance(prob, U, 0.5, 8, dt_log=dt_log)
     ctx.check()
+    # each step's dt from the CFL rule equals the oracle's
+    assert np.array_equal(_host(dt_log), np.array(dts))
     got = _host(U)
     assert np.abs(got - ref).max() <= FINAL_TOL * max(1.0, np.abs(ref).max())
 
