@@ -267,8 +267,8 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
         timed(ctx, PROF_SWEEP_X, [&] {
             DISPATCH_R(p.order,
                        if constexpr (scalar_lane_shared(R)) {
-                           // 64 kScalarKC - 2R cells per wave, four waves per block
-                           const long nw = (long)blocks_for(p.nx, 64 * kScalarKC - 2 * R);
+                           // DppTile<R>::CW cells per wave, four waves per block
+                           const long nw = (long)blocks_for(p.nx, DppTile<R>::CW);
                            hipLaunchKernelGGL((k_scalar_sweep_dpp<R>), dim3(blocks_for(nw, 4)), dim3(256), 0,
                                               ctx->stream, Us, (long)p.nx, 1.0 / p.hx, flux, p.adv_speed, split,
                                               p.bc_x, ax, so, idx, active);

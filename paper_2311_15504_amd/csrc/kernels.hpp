@@ -324,9 +324,9 @@ __global__ __launch_bounds__(TF) void k_scalar_sweep(const double* __restrict__ 
 // cells, and R to the left and R-1 to the right taken from the neighbouring
 // lanes by wavefront shifts (DPP wave_shr:1 / wave_shl:1 move all four values
 // of a lane one lane over: two 32-bit moves per double).  A wave covers
-// 64 KC = 256 cells and reconstructs the 257-2R faces whose 2R-cell windows
-// lie inside it; waves overlap by one face, so every cell's two faces come
-// from the same wave.  Four cells per lane keep four loads in flight per lane
+// 64 KC = 256 cells and reconstructs the faces whose 2R-cell windows lie
+// inside it; waves overlap by one face, so every cell's two faces come from
+// the same wave.  Four cells per lane keep four loads in flight per lane
 // and share each lane's registers between four windows.  No LDS, no barrier.
 // The windows hold the same values as the LDS sweep's, so the results are
 // the same bit for bit.  Shifts run with every lane of the wave active
@@ -384,6 +384,16 @@ __device__ __forceinline__ void gather_neighbours(const double (&v)[kScalarKC], 
     }
 }
 
+// Wave tiles start at even cells (RA = R rounded up to even cells of left
+// halo, an even number CW of cells written), so that a lane's cells pair up
+// into 16-byte aligned loads and stores away from the line's ends.
+template <int R>
+struct DppTile {
+    static constexpr int KC = kScalarKC;
+    static constexpr int RA = R + (R & 1);                    // left halo, even
+    static constexpr int CW = (64 * KC - RA - R) & ~1;        // cells written per wave
+};
+
 template <int R>
 __global__ __launch_bounds__(256) void k_scalar_sweep_dpp(const double* __restrict__ us, long n, double ih,
                                                           int flux, double a, int split, int bc,
@@ -393,20 +403,41 @@ __global__ __launch_bounds__(256) void k_scalar_sweep_dpp(const double* __restri
     if (active && *active == 0) return;
     constexpr int KC = kScalarKC;
     constexpr int W = 2 * R - 1;
-    constexpr int CW = 64 * KC - 2 * R;       // cells written per wave (faces per wave - 1)
+    constexpr int RA = DppTile<R>::RA, CW = DppTile<R>::CW;
+    static_assert(KC % 2 == 0, "cells pair up into 16-byte accesses");
     const int lane = threadIdx.x & 63;
     const long wave = blockIdx.x * 4L + (threadIdx.x >> 6);
-    const long base = wave * CW - R;          // the wave's first cell (wave-local cell 0)
+    const long base = wave * CW - RA;         // the wave's first cell (wave-local cell 0), even
+    const long c0 = base + KC * lane;         // the lane's first cell
+    // paired 16-byte accesses where the arrays allow them; the whole wave
+    // inside the line: paired loads, no index map
+    const bool aligned = (((uintptr_t)us | (uintptr_t)so.out | (so.stage ? (uintptr_t)so.Un : 0)) & 15) == 0;
+    const bool inner = aligned && base >= 0 && base + 64 * KC <= n;
     const double al = split ? *alpha : 0.0;
-    // own cells base + KC lane + k; the stage's U^n at the same cells
-    double u[KC], gp[KC], gm[KC], un[KC];
+    // own cells c0 .. c0+KC-1; the stage's U^n at the same cells
+    double u[KC], un[KC];
+    if (inner) {
 #pragma unroll
-    for (int k = 0; k < KC; ++k) u[k] = us[map_cell(base + KC * lane + k, n, bc)];
+        for (int k = 0; k < KC; k += 2) {
+            const double2 v = *reinterpret_cast<const double2*>(us + c0 + k);
+            u[k] = v.x;
+            u[k + 1] = v.y;
+        }
+        if (so.stage) {
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-        const long c = base + KC * lane + k;
-        un[k] = (so.stage && c >= 0 && c < n) ? so.Un[c] : 0.0;
+            for (int k = 0; k < KC; k += 2) {
+                const double2 v = *reinterpret_cast<const double2*>(so.Un + c0 + k);
+                un[k] = v.x;
+                un[k + 1] = v.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) u[k] = us[map_cell(c0 + k, n, bc)];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) un[k] = (so.stage && c0 + k >= 0 && c0 + k < n) ? so.Un[c0 + k] : 0.0;
     }
+    double gp[KC], gm[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         const double f = flux == SYS_ADVECTION ? a * u[k] : 0.5 * u[k] * u[k];
@@ -441,22 +472,31 @@ __global__ __launch_bounds__(256) void k_scalar_sweep_dpp(const double* __restri
         fh[j] = hp + hm;
     }
     const double fnext = from_right(fh[0]);   // the next lane's first face
-    const double ihv = ih;
+    const double dt = so.stage ? *so.dt : 0.0;
+    double res[KC];
+    bool ok[KC];
 #pragma unroll
     for (int j = 0; j < KC; ++j) {
         const int F = KC * lane + j;           // wave-local face index
         const long face = base + F;
-        if (F >= R && F <= 64 * KC - R && face <= n && idx) {
+        if (F >= RA && F <= RA + CW && face <= n && idx) {
             idx[2 * face] = (uint8_t)ip[j];
             idx[2 * face + 1] = (uint8_t)im[j];
         }
         const long cell = face;               // between faces F and F+1
-        if (F >= R && F <= 64 * KC - 1 - R && cell < n) {
-            const double right = j + 1 < KC ? fh[j + 1 < KC ? j + 1 : 0] : fnext;
-            double L = -((right - fh[j]) * ihv);
-            if (so.Lprev) L = so.Lprev[cell] + L;
-            if (so.stage == 0) so.out[cell] = L;
-            else so.out[cell] = rk_combine(so.stage, un[j], u[j], L, *so.dt);
+        ok[j] = F >= RA && F <= RA + CW - 1 && cell < n;
+        const double right = j + 1 < KC ? fh[j + 1 < KC ? j + 1 : 0] : fnext;
+        double L = -((right - fh[j]) * ih);
+        if (ok[j] && so.Lprev) L = so.Lprev[cell] + L;
+        res[j] = so.stage == 0 ? L : rk_combine(so.stage, un[j], u[j], L, dt);
+    }
+#pragma unroll
+    for (int j = 0; j < KC; j += 2) {
+        if (aligned && ok[j] && ok[j + 1]) {
+            *reinterpret_cast<double2*>(so.out + c0 + j) = make_double2(res[j], res[j + 1]);
+        } else {
+            if (ok[j]) so.out[c0 + j] = res[j];
+            if (ok[j + 1]) so.out[c0 + j + 1] = res[j + 1];
         }
     }
 }

@@ -320,3 +320,60 @@ def test_scalar_operator_many_waves_bitwise(ctx, order):
         got = ctx.rhs(enomr.Problem.scalar(enomr.BURGERS, n, h, order, bc, enomr.SPLIT_NONE), _dev(ub[None]))
         ctx.check()
         assert np.array_equal(_host(got)[0], ref)
+
+
+@pytest.mark.parametrize("order", [5, 7, 17])
+def test_smallest_1d_lines_bitwise(ctx, order):
+    # n = 2r + 1, the smallest line the library accepts: one wave or tile
+    # holds several periods (periodic) or mostly clamped copies (outflow).
+    import paper_2311_15504_amd as enomr
+    n = order + 2
+    _, h, u = workloads.advection_sines_step(order, n)
+    _, hE, U = workloads.euler1d_riemann_perturbed(order, n)
+    for bc in (enomr.PERIODIC, enomr.OUTFLOW):
+        ref = oracle.scalar_rhs(order, u, h, bc=bc)
+        got = ctx.rhs(enomr.Problem.scalar(enomr.ADVECTION, n, h, order, bc), _dev(u[None]))
+        assert np.array_equal(_host(got)[0], ref)
+        ub = 1.5 + u
+        ref = oracle.scalar_rhs(order, ub, h, flux=oracle.BURGERS, split=oracle.SPLIT_NONE, bc=bc)
+        got = ctx.rhs(enomr.Problem.scalar(enomr.BURGERS, n, h, order, bc, enomr.SPLIT_NONE), _dev(ub[None]))
+        assert np.array_equal(_host(got)[0], ref)
+        ref, ridx, _ = oracle.euler1d_rhs(order, U, hE, bc=bc, with_idx=True)
+        got, gidx = ctx.rhs(enomr.Problem.euler1d(n, hE, order, bc=bc), _dev(U), with_idx=True)
+        ctx.check()
+        assert np.array_equal(_host(gidx).reshape(-1, 3, 2), ridx)
+        assert np.array_equal(_host(got), ref)
+
+
+def test_zero_steps_leave_the_state_unchanged(ctx):
+    import paper_2311_15504_amd as enomr
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(2, 40, 30)
+    U = _dev(U0)
+    ctx.advance(enomr.Problem.euler2d(40, 30, hx, hy, 9), U, 0.5, 0)
+    ctx.check()
+    assert np.array_equal(_host(U), U0)
+
+
+def test_scalar_operator_on_unaligned_arrays(ctx):
+    # arrays that start 8 bytes past a 16-byte boundary take the lane-shared
+    # sweep's element-wise loads and stores
+    import torch
+    import paper_2311_15504_amd as enomr
+    order, n = 5, 5003
+    _, h, u = workloads.advection_sines_step(1, n)
+    ref = oracle.scalar_rhs(order, u, h)
+    big = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    big[1:] = torch.from_numpy(u).cuda()
+    U = big[1:].view(1, n)
+    assert U.data_ptr() % 16 == 8
+    got = ctx.rhs(enomr.Problem.scalar(enomr.ADVECTION, n, h, order), U)
+    ctx.check()
+    assert np.array_equal(_host(got)[0], ref)
+    # and a whole run, whose stage states live in the (aligned) workspace
+    dt_log = torch.zeros(5, dtype=torch.float64, device="cuda")
+    ctx.advance(enomr.Problem.scalar(enomr.ADVECTION, n, h, order), U, 0.5, 5, dt_log=dt_log)
+    ctx.check()
+    dts = _host(dt_log)
+    assert np.all(dts == dts[0])              # |a| = 1: the same CFL step every time
+    ref_run = oracle.scalar_ssprk3_run(order, u, h, float(dts[0]), nsteps=5)
+    assert np.array_equal(_host(U)[0], ref_run)
