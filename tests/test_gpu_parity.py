@@ -302,7 +302,7 @@ def test_runs_are_deterministic(ctx):
     assert np.array_equal(_host(A), _host(B))
 
 
-@pytest.mark.parametrize("order", [5, 9, 13, 17])
+@pytest.mark.parametrize("order", [5, 7, 9, 13, 17])
 def test_scalar_operator_many_waves_bitwise(ctx, order):
     # The scalar sweep shares windows lane to lane: many waves, a ragged last
     # wave and both boundary kinds, LF-split advection and unsplit Burgers.
