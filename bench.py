@@ -33,6 +33,7 @@ PEAK_FP64_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz
 # log-based count equals the oracle's instrumented count on the same data.
 ROE_OPS = 44            # Roe average and the entries of L and R in use
 PROJ_OPS = 20           # L G of one cell: u-c/u+c rows share 3, 4 + 4, u row 7, shear 2
+ROW_OPS = (7, 7, 2, 7)  # one row of L G: u-c, u, shear, u+c
 BACK_OPS = 24           # w-hat+ + w-hat- (4) and R w-hat (20)
 IS0_OPS = 11
 STAGE_OPS = 36          # per cell and sweep: primitives, LF split, sqrt(rho)
@@ -40,45 +41,54 @@ DIFF_OPS = {"x": 8, "y": 12}               # -(dF)/h, and the add of L_x in the 
 RK_OPS = {1: 8, 2: 20, 3: 20}              # per cell: the SSP-RK3 stage combination
 
 
-def pair_ops_table(order):
+def pair_ops_table(order, field):
     """Ops of one (field, sign) reconstruction by its logged candidate C.
 
-    C = 0: IS0, the full stencil's b_l chain and compare, its a_l chain.
-    C >= 1: IS0 and the failed full stencil, then the indicators of
-    candidates 1..C, the cheaper of the b_l chains scanned in list order and
-    one difference table of the window plus a compare per candidate tested;
-    then the chosen a_l chain, or minmod (7) when no candidate passes.
+    C = 0: IS0 and the compare of the full stencil's indicator (its b_l and
+    a_l values are projections of stencil sums, counted per face).
+    C >= 1: the same, then the field's row of L over the window cells beyond
+    the five centre cells, the indicators of candidates 1..C (the cheaper of
+    the b_l chains scanned in list order and one difference table of the
+    window plus a compare per candidate tested), then the chosen a_l chain,
+    or minmod (7) when no candidate passes.
     """
     import paper_2311_15504_amd as enomr
     mn, _, _ = enomr.coefficients(order)
     nc = mn.shape[0]
     r = (order + 1) // 2
+    w = 2 * r - 1
     last_full = nc - 4                      # candidates with m, n >= 1 are 0..nc-4
     table = (2 * r - 2) * (2 * r - 1) // 2 - 1
     chain = lambda c: 2 * (mn[c, 0] + mn[c, 1]) + 1
     tab = np.zeros(256)
-    tab[0] = IS0_OPS + chain(0) + 1 + chain(0)
+    tab[0] = IS0_OPS + 1
     for C in range(1, nc):
         tested = min(C, last_full)
         scan = sum(chain(c) + 1 for c in range(1, tested + 1))
-        e = IS0_OPS + chain(0) + 1 + min(scan, table + tested)
+        e = IS0_OPS + 1 + (w - 5) * ROW_OPS[field] + min(scan, table + tested)
         e += chain(C) if C <= last_full else 7
         tab[C] = e
     return tab
 
 
 def face_ops(order):
-    """Ops of one face besides its 8 reconstructions."""
+    """Ops of one face besides its 8 reconstructions: the Roe average, per
+    sign L G at the five centre cells, the a_l and b_l sums of the four
+    split-flux components over the full stencil and their projections, and
+    the back-projection."""
     r = (order + 1) // 2
-    return ROE_OPS + 2 * (2 * r - 1) * PROJ_OPS + BACK_OPS
+    w = 2 * r - 1
+    return ROE_OPS + 2 * (5 * PROJ_OPS + 2 * 4 * (2 * w - 1) + 2 * PROJ_OPS) + BACK_OPS
 
 
 def sweep_ops(order, nfaces, ncells, hist, direction, rk_stage=None):
     """Ops of one sweep: nfaces faces whose (field, sign) choices have the
-    histogram `hist` (counts per logged candidate), ncells cells."""
-    pair = pair_ops_table(order)
+    per-field histograms `hist` ([4][256] counts per logged candidate),
+    ncells cells."""
+    h = np.asarray(hist, dtype=np.float64).reshape(4, 256)
+    pairs = sum(float((h[q] * pair_ops_table(order, q)).sum()) for q in range(4))
     cell = STAGE_OPS + DIFF_OPS[direction] + (RK_OPS[rk_stage] if rk_stage else 0)
-    return nfaces * face_ops(order) + float((np.asarray(hist, dtype=np.float64) * pair).sum()) + ncells * cell
+    return nfaces * face_ops(order) + pairs + ncells * cell
 
 
 def run(args):
@@ -132,18 +142,19 @@ def run(args):
     ib = prob.idx_bytes()
     log = torch.empty(3 * ib, dtype=torch.uint8, device="cuda")
     nxf = n * (n + 1) * 8
-    hist_x = torch.zeros(256, dtype=torch.float64, device="cuda")
-    hist_y = torch.zeros(256, dtype=torch.float64, device="cuda")
+    hist_x = torch.zeros(4, 256, dtype=torch.float64, device="cuda")
+    hist_y = torch.zeros(4, 256, dtype=torch.float64, device="cuda")
     for _ in range(args.steps):
         dt = ctx.dt(prob, U, cfl)
         ctx.ssprk3_step(prob, U, dt, log)
         for s in range(3):
             seg = log[s * ib:(s + 1) * ib]
             # x faces: [ny][nx+1][4][2]; face nx repeats face 0 (periodic x)
-            xs = seg[:nxf].view(n, n + 1, 8)[:, :n, :].reshape(-1)
-            ys = seg[nxf:]
-            hist_x += torch.bincount(xs.long(), minlength=256).double()
-            hist_y += torch.bincount(ys.long(), minlength=256).double()
+            xs = seg[:nxf].view(n, n + 1, 4, 2)[:, :n]
+            ys = seg[nxf:].view(n + 1, n, 4, 2)
+            for q in range(4):
+                hist_x[q] += torch.bincount(xs[:, :, q, :].reshape(-1).long(), minlength=256).double()
+                hist_y[q] += torch.bincount(ys[:, :, q, :].reshape(-1).long(), minlength=256).double()
     ctx.check()
     launches = 3 * args.steps
     # x faces: n per periodic row (face n repeats face 0); y faces: n+1 per outflow column
@@ -160,8 +171,8 @@ def run(args):
     per_launch = fl / launches
     avg_ms = kms / nl
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
-    smooth_frac_x = float(hist_x[0] / hist_x.sum())
-    smooth_frac_y = float(hist_y[0] / hist_y.sum())
+    smooth_frac_x = float(hist_x[:, 0].sum() / hist_x.sum())
+    smooth_frac_y = float(hist_y[:, 0].sum() / hist_y.sum())
 
     out = {
         "metric": METRIC,

@@ -17,6 +17,11 @@
  *     component) order;
  *   - projections L G: the same chain from the last component to the first
  *     (rows u-c and u+c then share their last two terms);
+ *   - the full stencil of a characteristic field (candidate 0): its indicator
+ *     and flux are the projection of the stencil sums of the split fluxes,
+ *     l_k.(sum_l b_l G_l) and l_k.(sum_l a_l G_l), each component's sum in
+ *     ascending cell order (the same values as sum_l b_l (l_k.G_l) in exact
+ *     arithmetic, since the projection is linear);
  *   - IS of every other candidate: the (m+n)-th undivided difference of its
  *     cells in ascending order, by repeated differencing f_{i+1} - f_i;
  *   - IS0 second differences: (f_c - 2 f_{c-1}) + f_{c-2};
@@ -161,11 +166,23 @@ static double undivided_difference(const double *f, long first, int d)
 }
 
 /*
+ * The full stencil (candidate 0) of a characteristic field, evaluated by the
+ * caller: is_sum = l_k.(sum b_l G_l) (the indicator before |.|), flux =
+ * l_k.(sum a_l G_l), and the operations the field's window projection costs
+ * when the reconstruction has to go past candidate 0.
+ */
+typedef struct {
+    double is_sum, flux, fallback_ops;
+} full_stencil;
+
+/*
  * Reconstruct f-hat at face j+1/2 from cell values f (indexable from
  * j-r+1 to j+r).  sign = +1: f^+ (upwind on the left); sign = -1: f^-.
  * Writes the chosen candidate's position in the candidate list to *idx.
+ * pre (optional): candidate 0's indicator and flux, already evaluated.
  */
-static double recon_face(const orc_table *T, const double *f, long j, int sign, int *idx)
+static double recon_face(const orc_table *T, const double *f, long j, int sign, int *idx,
+                         const full_stencil *pre)
 {
     const int s = sign > 0 ? 1 : -1;
     const long c = sign > 0 ? j : j + 1;
@@ -186,7 +203,7 @@ static double recon_face(const orc_table *T, const double *f, long j, int sign, 
     for (int k = 0; k < T->ncand; ++k) {
         const int m = T->m[k], n = T->n[k];
         if (m >= 1 && n >= 1)
-            is[k] = k == 0 ? fabs(stencil_dot(T->b[k], m, n, f, c, s))
+            is[k] = k == 0 ? fabs(pre ? pre->is_sum : stencil_dot(T->b[k], m, n, f, c, s))
                            : fabs(undivided_difference(f, s > 0 ? c - m : c - n, m + n));
         else
             is[k] = 0.0;
@@ -200,14 +217,17 @@ static double recon_face(const orc_table *T, const double *f, long j, int sign, 
     for (int k = 0; k < T->ncand; ++k) {
         if (T->m[k] >= 1 && T->n[k] >= 1) {
             const int d = T->m[k] + T->n[k];
-            if (k == 0) OPS(2 * d + 1 + 1);     /* b_l chain and compare */
+            if (k == 0) OPS(pre ? 1 : 2 * d + 1 + 1);     /* (b_l chain and) compare */
             else { scan += 2 * d + 1 + 1; ++tested; }
             if (is[k] < is0) {
                 if (k > 0) OPS(scan < table + tested ? scan : table + tested);
-                OPS(2 * d + 1);                 /* a_l chain */
                 *idx = k;
+                if (k == 0 && pre) return pre->flux;
+                OPS(2 * d + 1);                 /* a_l chain */
                 return stencil_dot(T->a[k], T->m[k], T->n[k], f, c, s);
             }
+            /* past candidate 0: the field's window must be projected */
+            if (k == 0 && pre) OPS(pre->fallback_ops);
         }
     }
     OPS(scan < table + tested ? scan : table + tested);
@@ -242,7 +262,7 @@ int orc_recon_faces(const orc_table *T, int sign, long n, const double *f_with_h
     const int r = T->r;
     for (long i = 0; i < n; ++i) {
         int k;
-        fhat[i] = recon_face(T, f_with_halo, i + r - 1, sign, &k);
+        fhat[i] = recon_face(T, f_with_halo, i + r - 1, sign, &k, NULL);
         if (idx) idx[i] = (uint8_t)k;
     }
     return ORC_OK;
@@ -313,10 +333,10 @@ int orc_scalar_rhs(const orc_table *T, int flux, double a, int split, int bc, lo
     for (long f = 0; f <= n; ++f) {
         long j = f - 1 + g;           /* left cell of face f in the ghosted array */
         int kp, km;
-        double hp = recon_face(T, fp, j, +1, &kp);
+        double hp = recon_face(T, fp, j, +1, &kp, NULL);
         double hm = 0.0;
         km = 0;
-        if (split == ORC_SPLIT_LF) hm = recon_face(T, fm, j, -1, &km);
+        if (split == ORC_SPLIT_LF) hm = recon_face(T, fm, j, -1, &km, NULL);
         fh[f] = hp + hm;
         if (idx) { idx[2 * f] = (uint8_t)kp; idx[2 * f + 1] = (uint8_t)km; }
     }
@@ -562,8 +582,8 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
                     wm[i] = Gm[i * nv + k];
                 }
                 int kp, km;
-                double hp = recon_face(T, wp, j, +1, &kp);
-                double hm = recon_face(T, wm, j, -1, &km);
+                double hp = recon_face(T, wp, j, +1, &kp, NULL);
+                double hm = recon_face(T, wm, j, -1, &km, NULL);
                 Fhat[f * nv + k] = hp + hm;
                 if (idx) {
                     idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
@@ -577,10 +597,39 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
         /* Roe average and the entries of L and R used below (0.5 q^2 is shared
            by c^2 and R) */
         OPS(nv == 4 ? 44 : 36);
-        /* L G over each window (2r-1 cells per sign): rows u-c and u+c share
-           their last two terms (3), then 2 fma each; the u row 7 (5 in 1D); the
-           shear row one fma */
-        OPS(2 * (2 * T->r - 1) * (nv == 4 ? 20 : 14));
+        const int W = 2 * T->r - 1;
+        const double proj = nv == 4 ? 20 : 14;
+        /* the full stencil of every field by linearity: per sign the a_l and
+           b_l sums of each split-flux component, then their projections */
+        full_stencil pre[4][2];
+        if (!var.per_field) {
+            double A[2][4], B[2][4];
+            for (int sg = 0; sg < 2; ++sg) {
+                const double *G = sg == 0 ? Gp : Gm;
+                const long cc = sg == 0 ? j : j + 1;
+                const int ss = sg == 0 ? 1 : -1;
+                for (int v = 0; v < nv; ++v) {
+                    for (long i = j - T->r + 1; i <= j + T->r; ++i) wp[i] = G[i * nv + v];
+                    A[sg][v] = stencil_dot(T->a[0], T->m[0], T->n[0], wp, cc, ss);
+                    B[sg][v] = stencil_dot(T->b[0], T->m[0], T->n[0], wp, cc, ss);
+                }
+            }
+            for (int k = 0; k < nv; ++k)
+                for (int sg = 0; sg < 2; ++sg) {
+                    pre[k][sg].is_sum = project_dot(Lm[k], B[sg], nv);
+                    pre[k][sg].flux = project_dot(Lm[k], A[sg], nv);
+                    /* one row of L over the window cells beyond the five
+                       centre cells IS0 uses: u-c, u+c and u rows 3 fma and a
+                       product (2 fma and a product in 1D), the shear row one fma */
+                    pre[k][sg].fallback_ops = (W - 5) * (nv == 4 ? (k == 2 ? 2 : 7) : 5);
+                }
+            /* per sign: L G at the five centre cells, 2 nv chains of W terms,
+               and the projection of the a_l and b_l sums */
+            OPS(2 * (5 * proj + 2 * nv * (2 * W - 1) + 2 * proj));
+        } else {
+            /* L F and L U over each window (2r-1 cells per sign) */
+            OPS(2 * W * proj);
+        }
         double what[4];
         for (int k = 0; k < nv; ++k) {
             /* characteristic field k of the split fluxes over the face's window */
@@ -599,8 +648,8 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
                 }
             }
             int kp, km;
-            double hp = recon_face(T, wp, j, +1, &kp);
-            double hm = recon_face(T, wm, j, -1, &km);
+            double hp = recon_face(T, wp, j, +1, &kp, var.per_field ? NULL : &pre[k][0]);
+            double hm = recon_face(T, wm, j, -1, &km, var.per_field ? NULL : &pre[k][1]);
             what[k] = hp + hm;
             if (idx) {
                 idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
@@ -976,6 +1025,23 @@ static dual recon_frozen(const orc_table *T, const dual *f, long j, int sign, in
     return dadd(f0, dscale(0.5, mm));
 }
 
+/* The full stencil's a_l sum of component v of the split fluxes G ([cell][3]),
+   frame and cell order as in recon_face (dual arithmetic). */
+static dual full_sum_frozen(const orc_table *T, const dual *G, long j, int sign, int v)
+{
+    const int s = sign > 0 ? 1 : -1;
+    const long c = sign > 0 ? j : j + 1;
+    const int m = T->m[0], n = T->n[0];
+    int l = (s > 0) ? -m : n;
+    const int dl = (s > 0) ? 1 : -1;
+    dual acc = dmul(D(T->a[0][l + m]), G[(c + (long)s * l) * 3 + v]);
+    for (int q = 1; q < m + n + 1; ++q) {
+        l += dl;
+        acc = dfma(D(T->a[0][l + m]), G[(c + (long)s * l) * 3 + v], acc);
+    }
+    return acc;
+}
+
 /*
  * Frozen operator and tangent: L = L(U; idx, alpha), dL = dL/dU . dU.
  * U, dU, L, dL: [3][n]; idx: [n+1][3][2] as from orc_euler1d_rhs.  dU and dL
@@ -1048,6 +1114,13 @@ int orc_euler1d_rhs_frozen(const orc_table *T, double gamma, int bc, long n, dou
             {dsub(u, c), u, dadd(u, c)},
             {dsub(Hr, uc), dscale(0.5, q2), dadd(Hr, uc)},
         };
+        /* the full stencil's flux is the projection of the a_l sums (as in
+           euler_line_fluxes) */
+        dual Ap[3], Am[3];
+        for (int v = 0; v < 3; ++v) {
+            Ap[v] = full_sum_frozen(T, Gp, j, +1, v);
+            Am[v] = full_sum_frozen(T, Gm, j, -1, v);
+        }
         dual what[3];
         for (int q = 0; q < 3; ++q) {
             for (long i = j - T->r + 1; i <= j + T->r; ++i) {
@@ -1056,7 +1129,9 @@ int orc_euler1d_rhs_frozen(const orc_table *T, double gamma, int bc, long n, dou
             }
             int kp = idx[(f * 3 + q) * 2 + 0], km = idx[(f * 3 + q) * 2 + 1];
             if (kp >= T->ncand || km >= T->ncand) { st = ORC_EINVAL; goto done; }
-            what[q] = dadd(recon_frozen(T, wp, j, +1, kp), recon_frozen(T, wm, j, -1, km));
+            dual hp = kp == 0 ? dproject(Lm[q], Ap, 3) : recon_frozen(T, wp, j, +1, kp);
+            dual hm = km == 0 ? dproject(Lm[q], Am, 3) : recon_frozen(T, wm, j, -1, km);
+            what[q] = dadd(hp, hm);
         }
         for (int v = 0; v < 3; ++v) Fh[f * 3 + v] = ddot(Rm[v], what, 3);
     }

@@ -10,9 +10,10 @@ import oracle
 import workloads
 
 
-def _hist(idx, drop_last_face):
-    a = idx[:, :-1] if drop_last_face == "x" else idx
-    return np.bincount(a.reshape(-1).astype(np.int64), minlength=256)[:256]
+def _field_hist(idx):
+    """[4][256] counts of the logged candidates per field of idx [..][4][2]."""
+    return np.stack([np.bincount(idx[..., q, :].reshape(-1).astype(np.int64), minlength=256)[:256]
+                     for q in range(4)])
 
 
 @pytest.mark.parametrize("order", [9, 17])
@@ -25,19 +26,22 @@ def test_log_based_count_equals_instrumented_oracle(order, bcx, bcy):
     # ix: [ny][nx+1][4][2]; iy: [ny+1][nx][4][2]; a periodic line's last face repeats its first
     ixl = ix[:, :nx] if bcx == oracle.PERIODIC else ix
     iyl = iy[:ny] if bcy == oracle.PERIODIC else iy
-    hx_ = np.bincount(ixl.reshape(-1).astype(np.int64), minlength=256)[:256]
-    hy_ = np.bincount(iyl.reshape(-1).astype(np.int64), minlength=256)[:256]
+    hx_ = _field_hist(ixl)
+    hy_ = _field_hist(iyl)
     fx = ny * (nx if bcx == oracle.PERIODIC else nx + 1)
     fy = nx * (ny if bcy == oracle.PERIODIC else ny + 1)
     got = bench.sweep_ops(order, fx, nx * ny, hx_, "x") + bench.sweep_ops(order, fy, nx * ny, hy_, "y")
-    assert hx_[1:].sum() > 0 and hy_[1:].sum() > 0      # the data exercises the fallback
+    assert hx_[:, 1:].sum() > 0 and hy_[:, 1:].sum() > 0      # the data exercises the fallback
+    assert hx_[2, 1:].sum() > 0                               # the shear field's fallback too
     assert got == ops, (got, ops)
 
 
 def test_smooth_face_count_closed_form():
     # On smooth data every reconstruction takes the full stencil (C = 0): the
-    # count per face is the Roe/projection/back-projection part plus 8 times
-    # (IS0 + two (4r-3)-term chains + compare), per cell staging and difference.
+    # count per face is the Roe part, per sign five centre projections, the
+    # a_l and b_l sums of four components ((2r-1)-term chains) and their two
+    # projections, the back-projection, plus 8 times (IS0 + compare); per
+    # cell staging and difference.
     order, n = 17, 128
     r = (order + 1) // 2
     x = np.linspace(-1.0, 1.0, n, endpoint=False)
@@ -51,6 +55,7 @@ def test_smooth_face_count_closed_form():
                                            bcy=oracle.PERIODIC)
     assert not ix.any() and not iy.any()
     ny, nx = rho.shape
-    per_face = 44 + 2 * (2 * r - 1) * 20 + 24 + 8 * (11 + 2 * (2 * (2 * r - 2) + 1) + 1)
+    w = 2 * r - 1
+    per_face = 44 + 2 * (5 * 20 + 2 * 4 * (2 * w - 1) + 2 * 20) + 24 + 8 * (11 + 1)
     expect = (ny * nx + nx * ny) * per_face + nx * ny * (36 + 8) + nx * ny * (36 + 12)
     assert ops == expect
