@@ -839,30 +839,43 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
 
         // ---- smooth path: stream the window once, accumulating for every
         // field and sign the full-stencil indicator and flux and keeping the
-        // five central values for IS0.
+        // five central values for IS0.  With the characteristic operator the
+        // chains run over the split-flux components, and their sums are
+        // projected once (the projection is linear); only the five centre
+        // cells are projected cell by cell.  The other variants accumulate
+        // the characteristic values themselves.
         constexpr int P0 = cand_pool(R, 0);
+        constexpr bool SUMS = VAR == VAR_CHAR;
         double hp[NV], hm[NV];
         unsigned fail = 0;
         uint64_t idxw = 0;
-        // + sign: stream cells j-r+1 .. j+r-1 once, projecting G^+ onto every
-        // field and accumulating the full stencil's indicator and flux; the
-        // baseline indicator IS0 (Eq. Baseline_IS, centre j) is built as the
-        // centre cells go by.
+        // + sign: stream cells j-r+1 .. j+r-1 once, accumulating the full
+        // stencil's indicator and flux; the baseline indicator IS0
+        // (Eq. Baseline_IS, centre j) is built as the centre cells go by.
         {
             double is[NV], fl[NV], a[NV], b[NV], cc[NV], isl[NV], is0[NV];
 #pragma unroll
             for (int o = -R + 1; o <= R - 1; ++o) {
-                double w[NV];
-                char_values<NV, VAR, +1, NCL * TL>(e, sm.Gp, sm.Gm, af, lpos(tl, jp + o), w);
+                double w[NV], x[NV];
+                const int lp = lpos(tl, jp + o);
+                if constexpr (SUMS) {
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) x[q] = sm.Gp[q][lp];
+                    if (o >= -2 && o <= 2) project<NV>(e, x, w);
+                } else {
+                    char_values<NV, VAR, +1, NCL * TL>(e, sm.Gp, sm.Gm, af, lp, w);
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) x[q] = w[q];
+                }
                 const int ci = o + (R - 1);
 #pragma unroll
                 for (int q = 0; q < NV; ++q) {
                     if (o == -R + 1) {
-                        is[q] = kCoef.b[P0][ci] * w[q];
-                        fl[q] = kCoef.a[P0][ci] * w[q];
+                        is[q] = kCoef.b[P0][ci] * x[q];
+                        fl[q] = kCoef.a[P0][ci] * x[q];
                     } else {
-                        is[q] = fma(kCoef.b[P0][ci], w[q], is[q]);
-                        fl[q] = fma(kCoef.a[P0][ci], w[q], fl[q]);
+                        is[q] = fma(kCoef.b[P0][ci], x[q], is[q]);
+                        fl[q] = fma(kCoef.a[P0][ci], x[q], fl[q]);
                     }
                     if (o == -2) a[q] = w[q];
                     if (o == -1) b[q] = w[q];
@@ -883,6 +896,16 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
 #pragma unroll
                 for (int q = 0; q < NV; ++q) asm volatile("" : "+v"(is[q]), "+v"(fl[q]));
             }
+            if constexpr (SUMS) {
+                double ps[NV], pf[NV];
+                project<NV>(e, is, ps);
+                project<NV>(e, fl, pf);
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    is[q] = ps[q];
+                    fl[q] = pf[q];
+                }
+            }
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 hp[q] = fl[q];
@@ -901,17 +924,26 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             double is[NV], fl[NV], a[NV], b[NV], cc[NV], isr[NV], is0[NV];
 #pragma unroll
             for (int o = -R + 2; o <= R; ++o) {
-                double w[NV];
-                char_values<NV, VAR, -1, NCL * TL>(e, sm.Gp, sm.Gm, af, lpos(tl, jp + o), w);
+                double w[NV], x[NV];
+                const int lp = lpos(tl, jp + o);
+                if constexpr (SUMS) {
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) x[q] = sm.Gm[q][lp];
+                    if (o >= -1 && o <= 3) project<NV>(e, x, w);
+                } else {
+                    char_values<NV, VAR, -1, NCL * TL>(e, sm.Gp, sm.Gm, af, lp, w);
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) x[q] = w[q];
+                }
                 const int ci = R - o;
 #pragma unroll
                 for (int q = 0; q < NV; ++q) {
                     if (o == -R + 2) {
-                        is[q] = kCoef.b[P0][ci] * w[q];
-                        fl[q] = kCoef.a[P0][ci] * w[q];
+                        is[q] = kCoef.b[P0][ci] * x[q];
+                        fl[q] = kCoef.a[P0][ci] * x[q];
                     } else {
-                        is[q] = fma(kCoef.b[P0][ci], w[q], is[q]);
-                        fl[q] = fma(kCoef.a[P0][ci], w[q], fl[q]);
+                        is[q] = fma(kCoef.b[P0][ci], x[q], is[q]);
+                        fl[q] = fma(kCoef.a[P0][ci], x[q], fl[q]);
                     }
                     if (o == -1) a[q] = w[q];
                     if (o == 0) b[q] = w[q];
@@ -931,6 +963,16 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
                 // value in registers.
 #pragma unroll
                 for (int q = 0; q < NV; ++q) asm volatile("" : "+v"(is[q]), "+v"(fl[q]));
+            }
+            if constexpr (SUMS) {
+                double ps[NV], pf[NV];
+                project<NV>(e, is, ps);
+                project<NV>(e, fl, pf);
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    is[q] = ps[q];
+                    fl[q] = pf[q];
+                }
             }
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
