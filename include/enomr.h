@@ -244,7 +244,7 @@ enomr_status enomr_adjoint_steps(enomr_ctx *ctx, const enomr_problem *prob, int6
  * 5..17), U[nprob] device pointers to the problems' states ([3][nx] or
  * [4][ny][nx]), bound to the batch for its lifetime and advanced in place.
  * The batch allocates its own workspace (2 stage states per problem; for 2D
- * also L_x and the per-line alphas).  autotune = 1 times one step of the 1D
+ * also L_y and the per-line alphas).  autotune = 1 times one step of the 1D
  * problems on scratch copies for each tile width (64, 128, 256 faces) and
  * keeps the fastest; 0 uses 128; 64, 128 or 256 use that width; any other
  * value is ENOMR_EINVAL.  2D problems use the 64 x 4 tiles of the

@@ -303,36 +303,39 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
         HIP_TRY(hipGetLastError());
         return ENOMR_OK;
     }
-    // 2D: x sweep stores L_x into the workspace, the y sweep adds L_y and
-    // either stores the sum or combines the RK stage.
-    double* Lx = at<double>(ws, w.L);
-    StageOut sx;
-    sx.Un = nullptr;
-    sx.Lprev = nullptr;
-    sx.out = Lx;
-    sx.dt = nullptr;
-    sx.stage = 0;
-    in.alpha = ax;
-    in.idx = idx;
-    in.ih = 1.0 / p.hx;
-    in.bc = p.bc_x;
-    timed(ctx, PROF_SWEEP_X, [&] {
-        DISPATCH_VAR(var, DISPATCH_R(p.order,
-                   hipLaunchKernelGGL((k_euler_sweep<4, R, 0, kTFx, kTLx, V>),
-                                      dim3(blocks_for(p.nx, kTFx - 1) * blocks_for(p.ny, kTLx)), dim3(kTFx * kTLx),
-                                      0, ctx->stream, in, sx)));
-    });
-    HIP_TRY(hipGetLastError());
+    // 2D: the y sweep stores L_y into the workspace, then the x sweep adds
+    // L_x (L_y + L_x = L_x + L_y exactly) and the source, and either stores
+    // the sum or combines the RK stage: the output phase with its extra reads
+    // runs in the sweep whose lines are rows, so those reads are coalesced.
+    double* Ly = at<double>(ws, w.L);
+    StageOut sy;
+    sy.Un = nullptr;
+    sy.Lprev = nullptr;
+    sy.out = Ly;
+    sy.dt = nullptr;
+    sy.stage = 0;
     in.alpha = ay;
     in.idx = idx ? idx + (size_t)p.ny * (p.nx + 1) * 8 : nullptr;
     in.ih = 1.0 / p.hy;
     in.bc = p.bc_y;
-    in.grav = p.gravity;
-    so.Lprev = Lx;
+    in.grav = 0.0;
     timed(ctx, PROF_SWEEP_Y, [&] {
         DISPATCH_VAR(var, DISPATCH_R(p.order,
                    hipLaunchKernelGGL((k_euler_sweep<4, R, 1, kTFy, kTLy, V>),
                                       dim3(blocks_for(p.ny, kTFy - 1) * blocks_for(p.nx, kTLy)), dim3(kTFy * kTLy),
+                                      0, ctx->stream, in, sy)));
+    });
+    HIP_TRY(hipGetLastError());
+    in.alpha = ax;
+    in.idx = idx;
+    in.ih = 1.0 / p.hx;
+    in.bc = p.bc_x;
+    in.grav = p.gravity;
+    so.Lprev = Ly;
+    timed(ctx, PROF_SWEEP_X, [&] {
+        DISPATCH_VAR(var, DISPATCH_R(p.order,
+                   hipLaunchKernelGGL((k_euler_sweep<4, R, 0, kTFx, kTLx, V>),
+                                      dim3(blocks_for(p.nx, kTFx - 1) * blocks_for(p.ny, kTLx)), dim3(kTFx * kTLx),
                                       0, ctx->stream, in, so)));
     });
     HIP_TRY(hipGetLastError());

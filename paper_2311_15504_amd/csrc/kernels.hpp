@@ -251,7 +251,7 @@ __device__ __forceinline__ double rk_combine(int stage, double un, double us, do
 
 struct StageOut {
     const double* Un;      // step-start state (RK mode)
-    const double* Lprev;   // operator part to add first (2D y-sweep), nullable
+    const double* Lprev;   // operator part to add first (2D: L_y in the x sweep), nullable
     double* out;           // L (store mode) or the next stage state (RK mode)
     const double* dt;      // device dt (RK mode)
     int stage;             // 1..3; 0 = store L
@@ -629,7 +629,7 @@ struct SweepIn {
     const int* active;     // nullable
     long nx, ny;
     double ih, gamma;
-    double grav;           // 2D y sweep: source g [0, 0, rho, rho v] (0: none)
+    double grav;           // 2D, the sweep adding the other's L: source g [0, 0, rho, rho v] (0: none)
     int bc;
 };
 
@@ -1047,8 +1047,9 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     const bool outc = gl < nlines && tf < TC && cell < n;
     const long g = outc ? gidx(gl, cell) : 0;
     double lp[NV], un[NV], us[NV];
-    // the source of the 2D y sweep: rho and rho v of the cell
-    constexpr bool SRC = DIR == 1 && NV == 4;
+    // the source, added by the 2D sweep that completes the operator: rho and
+    // rho v of the cell
+    constexpr bool SRC = NV == 4;
     double s_rho = 0.0, s_rv = 0.0;
     if (outc) {
 #pragma unroll
@@ -1250,7 +1251,7 @@ __global__ __launch_bounds__(TF, 4) void k_batch_euler1d(const BatchProb* __rest
 // ---------------------------------------------------------------------------
 // Batched 2D Euler problems: one 256-thread workgroup advances a whole
 // problem, each stage as per-line alphas (a wave per row, then per column),
-// dt at the first stage, the x sweep into L_x and the y sweep with the RK
+// dt at the first stage, the y sweep into L_y and the x sweep with the RK
 // combination, over the same 64 x 4 tiles as the single-problem kernels, so
 // every problem's result equals its single-problem run bit for bit.
 // ---------------------------------------------------------------------------
@@ -1259,7 +1260,7 @@ struct BatchProb2 {
     double* U;       // [4][ny][nx] state, advanced in place
     double* U1;      // stage states (workspace)
     double* U2;
-    double* L;       // L_x (workspace)
+    double* L;       // L_y (workspace)
     double* ax;      // [ny] alphas of the rows
     double* ay;      // [nx] alphas of the columns
     long nx, ny;
@@ -1354,33 +1355,33 @@ __device__ __forceinline__ void run_problem_2d(const BatchProb2& P, const BatchP
             in.ny = ny;
             in.gamma = P.gamma;
             in.grav = 0.0;
-            // x sweep: L_x into P.L
-            in.alpha = P.ax;
-            in.ih = P.ihx;
-            in.bc = P.bcx;
-            StageOut sx;
-            sx.Un = nullptr;
-            sx.Lprev = nullptr;
-            sx.out = P.L;
-            sx.dt = nullptr;
-            sx.stage = 0;
-            for (long l0 = 0; l0 < ny; l0 += kB2TL)
-                for (long c0 = 0; c0 < nx; c0 += kB2TF - 1)
-                    sweep_tile<4, R, 0, kB2TF, kB2TL, kB2NCL>(in, sx, l0, c0, sm);
-            __syncthreads();
-            // y sweep: adds L_y and combines the RK stage
+            // y sweep: L_y into P.L
             in.alpha = P.ay;
             in.ih = P.ihy;
             in.bc = P.bcy;
             StageOut sy;
-            sy.Un = P.U;
-            sy.Lprev = P.L;
-            sy.out = out;
-            sy.dt = s_dt;
-            sy.stage = stage;
+            sy.Un = nullptr;
+            sy.Lprev = nullptr;
+            sy.out = P.L;
+            sy.dt = nullptr;
+            sy.stage = 0;
             for (long l0 = 0; l0 < nx; l0 += kB2TL)
                 for (long c0 = 0; c0 < ny; c0 += kB2TF - 1)
                     sweep_tile<4, R, 1, kB2TF, kB2TL, kB2NCL>(in, sy, l0, c0, sm);
+            __syncthreads();
+            // x sweep: adds L_x and combines the RK stage
+            in.alpha = P.ax;
+            in.ih = P.ihx;
+            in.bc = P.bcx;
+            StageOut sx;
+            sx.Un = P.U;
+            sx.Lprev = P.L;
+            sx.out = out;
+            sx.dt = s_dt;
+            sx.stage = stage;
+            for (long l0 = 0; l0 < ny; l0 += kB2TL)
+                for (long c0 = 0; c0 < nx; c0 += kB2TF - 1)
+                    sweep_tile<4, R, 0, kB2TF, kB2TL, kB2NCL>(in, sx, l0, c0, sm);
             __syncthreads();
         }
     }
