@@ -274,6 +274,15 @@ __global__ __launch_bounds__(TF) void k_scalar_sweep(const double* __restrict__ 
     __shared__ double sp[NCL], sm[NCL], sf[TF];
     const long c0 = blockIdx.x * (long)TC;
     const double al = split ? *alpha : 0.0;
+    // the output cell's operands, requested first so that their latency
+    // overlaps the staging and the reconstruction
+    const int tf = threadIdx.x;
+    const long cell = c0 + tf;
+    const bool outc = tf < TC && cell < n;
+    const double lp_c = (outc && so.Lprev) ? so.Lprev[cell] : 0.0;
+    const double un_c = (outc && so.stage) ? so.Un[cell] : 0.0;
+    const double us_c = (outc && so.stage) ? us[cell] : 0.0;
+    const double dt_c = so.stage ? *so.dt : 0.0;
     for (int e = threadIdx.x; e < NCL; e += TF) {
         const double u = us[map_cell(c0 - R + e, n, bc)];
         const double f = flux == SYS_ADVECTION ? a * u : 0.5 * u * u;
@@ -287,7 +296,6 @@ __global__ __launch_bounds__(TF) void k_scalar_sweep(const double* __restrict__ 
         }
     }
     __syncthreads();
-    const int tf = threadIdx.x;
     const long face = c0 + tf;
     if (face <= n) {
         const int jp = tf + R - 1;   // left cell of the face in LDS
@@ -308,12 +316,11 @@ __global__ __launch_bounds__(TF) void k_scalar_sweep(const double* __restrict__ 
         }
     }
     __syncthreads();
-    const long cell = c0 + tf;
-    if (tf < TC && cell < n) {
+    if (outc) {
         double L = -((sf[tf + 1] - sf[tf]) * ih);
-        if (so.Lprev) L = so.Lprev[cell] + L;
+        if (so.Lprev) L = lp_c + L;
         if (so.stage == 0) so.out[cell] = L;
-        else so.out[cell] = rk_combine(so.stage, so.Un[cell], us[cell], L, *so.dt);
+        else so.out[cell] = rk_combine(so.stage, un_c, us_c, L, dt_c);
     }
 }
 
