@@ -267,10 +267,11 @@ def run_batched(args):
 
 
 def run_batched_2d(args):
-    """Batched 2D workload: independent 2D Euler problems, nx, ny ~ U{32..192},
-    orders {7, 9, 13, 17}, seeded quadrants + vortices, x periodic / y outflow,
-    `batch_steps` SSP-RK3 steps in one graph launch of the persistent 2D kernel,
-    against per-problem launches of a sample of the same problems."""
+    """Batched 2D workload: 1024 independent 2D Euler problems (by default),
+    nx, ny ~ U{32..128}, orders {7, 9, 13, 17}, seeded quadrants + vortices, x
+    periodic / y outflow, `batch2d_steps` SSP-RK3 steps in one graph launch of
+    the persistent 2D kernel, against per-problem launches of a sample of the
+    same problems."""
     import torch
 
     import paper_2311_15504_amd as enomr
@@ -278,7 +279,7 @@ def run_batched_2d(args):
 
     cfl = 0.5
     steps = args.batch2d_steps
-    plist = workloads.batched_problems_2d(args.seed, nprob=args.batch2d_problems)
+    plist = workloads.batched_problems_2d(args.seed, nprob=args.batch2d_problems, nmax=args.batch2d_nmax)
     probs = [enomr.Problem.euler2d(p["nx"], p["ny"], p["hx"], p["hy"], p["order"]) for p in plist]
     host = [p["U"] for p in plist]
     states = [torch.from_numpy(U).cuda() for U in host]
@@ -317,8 +318,9 @@ def run_batched_2d(args):
     same = all(torch.equal(states[i], Us[k]) for k, i in enumerate(sample))
     batch.close()
     ctx.close()
-    return {"workload": "%d independent 2D Euler problems, nx, ny ~ U{32..192}, orders {7,9,13,17}, seeded "
-                        "quadrants + vortices, %d SSP-RK3 steps at CFL 0.5, one graph launch" % (len(plist), steps),
+    return {"workload": "%d independent 2D Euler problems, nx, ny ~ U{32..%d}, orders {7,9,13,17}, seeded "
+                        "quadrants + vortices, %d SSP-RK3 steps at CFL 0.5, one graph launch"
+                        % (len(plist), args.batch2d_nmax, steps),
             "value": value, "unit": "cell-updates/s", "ms": ms, "total_cells": cells,
             "workgroups": info["workgroups"],
             "per_problem_launches": {"value": value_pp, "sample_problems": int(len(sample)), "ms": ms_pp},
@@ -569,8 +571,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-sample", type=int, default=64)
     ap.add_argument("--no-batched-2d", action="store_true")
-    ap.add_argument("--batch2d-problems", type=int, default=256)
+    ap.add_argument("--batch2d-problems", type=int, default=1024)
     ap.add_argument("--batch2d-steps", type=int, default=20)
+    ap.add_argument("--batch2d-nmax", type=int, default=128)
     ap.add_argument("--no-scalar", action="store_true")
     ap.add_argument("--scalar-n", type=int, default=1 << 27)
     ap.add_argument("--scalar-steps", type=int, default=10)

@@ -152,3 +152,31 @@ def test_batch_rejects_bad_problems(ctx):
     p1 = enomr.Problem.euler1d(100, h, 9)
     with pytest.raises(enomr.EnomrError):
         enomr.Batch(ctx, [p1], [torch.from_numpy(U1).cuda()], tile_faces=96)
+
+
+def test_batch_reports_a_problem_the_method_drives_non_physical(ctx):
+    # One seeded 32 x 39 order-17 problem whose under-resolved vortices drive
+    # the pressure negative within 20 steps; the oracle fails on it the same
+    # way.  In a batch the status is latched, and the other problems still
+    # equal their single-problem runs bit for bit.
+    import torch
+    import paper_2311_15504_amd as enomr
+    plist = workloads.batched_problems_2d(0, nprob=374, nmax=96)
+    bad = plist[373]
+    assert (bad["nx"], bad["ny"], bad["order"]) == (32, 39, 17)
+    with pytest.raises(oracle.OracleError):
+        oracle.euler2d_run(bad["order"], bad["U"], bad["hx"], bad["hy"], 20, cfl=0.5)
+    chosen = [plist[5], bad, plist[11]]
+    probs = [enomr.Problem.euler2d(p["nx"], p["ny"], p["hx"], p["hy"], p["order"]) for p in chosen]
+    states = [torch.from_numpy(p["U"]).cuda() for p in chosen]
+    batch = enomr.Batch(ctx, probs, states, autotune=False)
+    batch.advance(0.5, 20)
+    with pytest.raises(enomr.EnomrError) as e:
+        ctx.check()
+    assert e.value.status == 5
+    for k in (0, 2):
+        U = torch.from_numpy(chosen[k]["U"]).cuda()
+        ctx.advance(probs[k], U, 0.5, 20)
+        ctx.check()
+        assert torch.equal(U, states[k])
+    batch.close()
