@@ -227,8 +227,9 @@ enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* 
     const long na = pf ? 3 : 1;
     const long nax = na * p.ny, nay = na * (p.ndim == 2 ? p.nx : 1);
     timed(ctx, PROF_AUX, [&] {
-        hipLaunchKernelGGL(k_fill, dim3(blocks_for(nax, 256)), dim3(256), 0, ctx->stream, ax, nax, 0.0);
-        hipLaunchKernelGGL(k_fill, dim3(blocks_for(nay, 256)), dim3(256), 0, ctx->stream, ay, nay, 0.0);
+        // ay follows ax in the workspace: one fill clears both (and the padding between)
+        const long nfill = (long)(w.ay - w.ax) / (long)sizeof(double) + nay;
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(nfill, 256)), dim3(256), 0, ctx->stream, ax, nfill, 0.0);
         if (p.system == ENOMR_EULER) {
             dim3 grid(blocks_for(p.nx, 64), blocks_for(p.ny, 32));
             if (pf && p.ndim == 2)
