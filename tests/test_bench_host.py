@@ -1,0 +1,66 @@
+"""Host-side logic of bench.py: the one-GPU contract and the counter summary
+(scaling of FETCH_SIZE / WRITE_SIZE by the calibration copy).  No GPU."""
+import csv
+import json
+import os
+import re
+import subprocess
+import sys
+
+import bench
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def _counter_csv(path, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "p_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def test_traffic_summary_scales_counters_by_the_copy(tmp_path):
+    xk = "void enomr::k_euler_sweep<4, 9, 0, 64, 4, 0>(enomr::SweepIn, enomr::StageOut)"
+    yk = "void enomr::k_euler_sweep<4, 9, 1, 64, 4, 0>(enomr::SweepIn, enomr::StageOut)"
+    cp = "__amd_rocclr_copyBuffer"
+    # two dispatches per sweep, each counter split over two instances; the
+    # copy of 1024 MiB reads as 512 MiB fetched and 1024 MiB written
+    def rows(counter, xv, yv, copy):
+        out = []
+        for d, k, v in ((1, xk, xv), (2, xk, xv), (3, yk, yv), (4, yk, yv), (5, cp, copy), (6, cp, 1.0)):
+            out += [{"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v / 2}] * 2
+        return out
+    _counter_csv(str(tmp_path / "fetch"), rows("FETCH_SIZE", 1000.0, 3000.0, 512 * 1024.0))
+    _counter_csv(str(tmp_path / "write"), rows("WRITE_SIZE", 2000.0, 500.0, 1024 * 1024.0))
+    _counter_csv(str(tmp_path / "valu"), rows("SQ_INSTS_VALU", 7.0, 9.0, 1.0))
+    text = bench.traffic_summary(str(tmp_path / "fetch"), str(tmp_path / "write"), str(tmp_path / "valu"),
+                                 1024, "cmd")
+    rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+    assert rec["calibration"]["fetch_scale"] == 2.0 and rec["calibration"]["write_scale"] == 1.0
+    assert rec["bytes_per_launch"]["k_euler_sweep (x faces)"] == (1000.0 * 2 + 2000.0) * 1024
+    assert rec["bytes_per_launch"]["k_euler_sweep (y faces)"] == (3000.0 * 2 + 500.0) * 1024
+    assert rec["valu_wave_instr_per_launch"] == {"k_euler_sweep (x faces)": 7.0, "k_euler_sweep (y faces)": 9.0}
+    assert rec["source_sha256"] == bench.sweep_source_hash()
+
+
+def test_face_count_grows_with_order_and_pairs_cost_more_past_the_full_stencil():
+    prev = 0
+    for order in (5, 9, 13, 17):
+        f = bench.face_ops(order)
+        assert f > prev
+        prev = f
+        nc = oracle.ncand(order)
+        for q in range(4):
+            t = bench.pair_ops_table(order, q)
+            assert t[0] == bench.IS0_OPS + 1
+            assert (t[1:nc] > t[0]).all() and not t[nc:].any()
