@@ -776,16 +776,32 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     auto fpos = [](int line, int f) { return DIR == 0 ? line * TF + f : f * TL + line; };
     auto gidx = [nx](long line, long cell) { return DIR == 0 ? line * nx + cell : cell * nx + line; };
 
-    // ---- stage the tile: primitives, LF split G = (F +- alpha U)/2, Roe inputs
-    for (int e = threadIdx.x; e < NCU * TL; e += NT) {
+    // ---- stage the tile: primitives, LF split G = (F +- alpha U)/2, Roe inputs.
+    // A thread stages up to NIT cells; all their loads are issued before any
+    // is used, so the staging costs one memory round trip, not NIT.
+    constexpr int NE = NCU * TL;
+    constexpr int NIT = (NE + NT - 1) / NT;
+    double Ust[NIT][NV];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = threadIdx.x + it * NT;
         const int line = DIR == 0 ? e / NCU : e % TL;
         const int cell = DIR == 0 ? e % NCU : e / TL;
         const long gl = line0 + line;
-        if (gl >= nlines) continue;
-        const long g = gidx(gl, map_cell(c0 - R + cell, n, in.bc));
-        double Uc[NV];
+        if (e < NE && gl < nlines) {
+            const long g = gidx(gl, map_cell(c0 - R + cell, n, in.bc));
 #pragma unroll
-        for (int q = 0; q < NV; ++q) Uc[q] = in.Us[gvar(q) * plane + g];
+            for (int q = 0; q < NV; ++q) Ust[it][q] = in.Us[gvar(q) * plane + g];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = threadIdx.x + it * NT;
+        const int line = DIR == 0 ? e / NCU : e % TL;
+        const int cell = DIR == 0 ? e % NCU : e / TL;
+        const long gl = line0 + line;
+        if (!(e < NE && gl < nlines)) continue;
+        const double (&Uc)[NV] = Ust[it];
         const double rho = Uc[0], mn = Uc[1], E = Uc[NV - 1];
         const double mt = NV == 4 ? Uc[2] : 0.0;
         const double ir = 1.0 / rho;
