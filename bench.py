@@ -368,7 +368,7 @@ def run_scalar(args):
         value = n * 3 * steps / (ms * 1e-3)
         sweep_ms, sweeps = prof["sweep_x"]
         gbs = SCALAR_BYTES_PER_CELL_STAGE * n * sweeps / (sweep_ms * 1e-3) / 1e9
-        kern = "k_scalar_sweep_dpp (windows shared lane to lane)" if order <= 7 else "k_scalar_sweep (LDS windows)"
+        kern = "k_scalar_sweep_dpp (windows shared lane to lane)" if order == 5 else "k_scalar_sweep (LDS windows)"
         out["order%d" % order] = {"kernel": kern, "value": value, "unit": "cell-updates/s", "ms_per_step": ms / steps,
                                   "sweep_us": 1e3 * sweep_ms / sweeps,
                                   "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",

@@ -208,10 +208,10 @@ void timed(enomr_ctx* ctx, int cls, F&& launch)
 constexpr int kTF1 = 64;                  // 1D lines
 // Scalar laws: windows shared lane to lane (k_scalar_sweep_dpp) or staged in
 // LDS (k_scalar_sweep), per order by measurement on MI355X (1D advection,
-// 2^27 nodes): lane sharing is 27% faster at order 5 and 12% at order 7, and
-// 15% to 33% slower from order 9 up, where its register windows (4 cells per
-// lane) lower the occupancy to 2-4 waves per SIMD.
-constexpr bool scalar_lane_shared(int R) { return R <= 4; }
+// 2^27 nodes): lane sharing is 1% faster at order 5 and slower from order 7
+// up, where its register windows (4 cells per lane) lower the occupancy to
+// 2-4 waves per SIMD.
+constexpr bool scalar_lane_shared(int R) { return R == 3; }
 constexpr int kMaxLsspStages = 18;        // linear SSP-RK(m, m-1): m up to order 17 + 1
 constexpr int kTFx = 64, kTLx = 4;        // 2D x sweep
 constexpr int kTFy = 64, kTLy = 4;        // 2D y sweep

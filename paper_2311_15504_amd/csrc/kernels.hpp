@@ -283,8 +283,19 @@ __global__ __launch_bounds__(TF) void k_scalar_sweep(const double* __restrict__ 
     const double un_c = (outc && so.stage) ? so.Un[cell] : 0.0;
     const double us_c = (outc && so.stage) ? us[cell] : 0.0;
     const double dt_c = so.stage ? *so.dt : 0.0;
-    for (int e = threadIdx.x; e < NCL; e += TF) {
-        const double u = us[map_cell(c0 - R + e, n, bc)];
+    // all of a thread's staging loads first: one memory round trip
+    constexpr int NIT = (NCL + TF - 1) / TF;
+    double ust[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = threadIdx.x + it * TF;
+        if (e < NCL) ust[it] = us[map_cell(c0 - R + e, n, bc)];
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = threadIdx.x + it * TF;
+        if (e >= NCL) continue;
+        const double u = ust[it];
         const double f = flux == SYS_ADVECTION ? a * u : 0.5 * u * u;
         if (split) {
             const double t = al * u;
