@@ -396,7 +396,7 @@ enomr_status rk3_step(enomr_ctx* ctx, const enomr_problem& p, double* U, const d
 
 // One reverse stage of the frozen 1D Euler operator (see AdjIn): one launch,
 // kAdjT cells per workgroup.
-constexpr int kAdjT = 64, kAdjNT = 128;
+constexpr int kAdjT = 32, kAdjNT = 128;
 
 enomr_status launch_adjoint_stage(enomr_ctx* ctx, const enomr_problem& p, AdjIn a)
 {
