@@ -793,6 +793,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     constexpr int NE = NCU * TL;
     constexpr int NIT = (NE + NT - 1) / NT;
     double Ust[NIT][NV];
+    __builtin_amdgcn_s_setprio(2);   // issue this tile's loads ahead of other waves' arithmetic
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int e = threadIdx.x + it * NT;
@@ -805,6 +806,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             for (int q = 0; q < NV; ++q) Ust[it][q] = in.Us[gvar(q) * plane + g];
         }
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int e = threadIdx.x + it * NT;
