@@ -284,7 +284,7 @@ def run_batched_2d(args):
     host = [p["U"] for p in plist]
     states = [torch.from_numpy(U).cuda() for U in host]
     ctx = enomr.Context(0)
-    batch = enomr.Batch(ctx, probs, states, autotune=False)
+    batch = enomr.Batch(ctx, probs, states, autotune=True)
     info = batch.info()
     batch.advance(cfl, 1)                           # warm-up step
     ctx.check()
@@ -322,7 +322,8 @@ def run_batched_2d(args):
                         "quadrants + vortices, %d SSP-RK3 steps at CFL 0.5, one graph launch"
                         % (len(plist), args.batch2d_nmax, steps),
             "value": value, "unit": "cell-updates/s", "ms": ms, "total_cells": cells,
-            "workgroups": info["workgroups"],
+            "workgroups": info["workgroups"], "tile2d": list(info["tile2d"]),
+            "autotune_ms_per_step": {"%dx%d" % sh: t for sh, t in zip(((64, 4), (32, 8), (16, 16)), info["tune2d_ms"])},
             "per_problem_launches": {"value": value_pp, "sample_problems": int(len(sample)), "ms": ms_pp},
             "speedup_vs_per_problem": value / value_pp, "sample_bitwise_equal": bool(same)}
 

@@ -247,12 +247,20 @@ enomr_status enomr_adjoint_steps(enomr_ctx *ctx, const enomr_problem *prob, int6
  * also L_y and the per-line alphas).  autotune = 1 times one step of the 1D
  * problems on scratch copies for each tile width (64, 128, 256 faces) and
  * keeps the fastest; 0 uses 128; 64, 128 or 256 use that width; any other
- * value is ENOMR_EINVAL.  2D problems use the 64 x 4 tiles of the
- * single-problem kernels.
+ * value is ENOMR_EINVAL.  autotune = 1 also times one step of the 2D
+ * problems for each tile shape of the 2D kernel (64 x 4, 32 x 8, 16 x 16
+ * faces x lines) and keeps the fastest; otherwise the 2D kernel uses 32 x 8.
+ * The tile shape does not change any result.
  * enomr_batch_advance: nsteps SSP-RK3 steps of every problem at CFL `cfl`.
  * enomr_batch_info: the 1D kernel's tile width, the workgroups of both
  * kernels, and the autotune times (ms, for widths 64/128/256; zeros without
  * autotune).  Any pointer may be NULL.
+ * enomr_batch_info2d: the 2D kernel's tile shape and its autotune times (ms,
+ * for 64 x 4, 32 x 8, 16 x 16; zeros without autotune).  Any pointer may be
+ * NULL.
+ * enomr_batch_set_tile2d: use the 2D tile shape tile_faces x tile_lines (one
+ * of the three) from the next advance on; waits for the context's stream and
+ * rebuilds the graph.  Other shapes: ENOMR_EINVAL.
  */
 typedef struct enomr_batch enomr_batch;
 enomr_status enomr_batch_create(enomr_ctx *ctx, int32_t nprob, const enomr_problem *probs, double *const *U,
@@ -260,6 +268,9 @@ enomr_status enomr_batch_create(enomr_ctx *ctx, int32_t nprob, const enomr_probl
 enomr_status enomr_batch_advance(enomr_batch *batch, double cfl, int64_t nsteps);
 enomr_status enomr_batch_info(const enomr_batch *batch, int32_t *tile_faces, int32_t *workgroups,
                               double *tune_ms);
+enomr_status enomr_batch_info2d(const enomr_batch *batch, int32_t *tile_faces, int32_t *tile_lines,
+                                double *tune_ms);
+enomr_status enomr_batch_set_tile2d(enomr_batch *batch, int32_t tile_faces, int32_t tile_lines);
 enomr_status enomr_batch_destroy(enomr_batch *batch);
 
 #ifdef __cplusplus

@@ -111,6 +111,8 @@ def lib():
             "enomr_batch_create": ([_vp, ctypes.c_int32, P, _vp, ctypes.c_int, ctypes.POINTER(_vp)], st),
             "enomr_batch_advance": ([_vp, ctypes.c_double, ctypes.c_int64], st),
             "enomr_batch_info": ([_vp, _vp, _vp, _vp], st),
+            "enomr_batch_info2d": ([_vp, _vp, _vp, _vp], st),
+            "enomr_batch_set_tile2d": ([_vp, ctypes.c_int32, ctypes.c_int32], st),
             "enomr_batch_destroy": ([_vp], st),
         }
         for name, (args, res) in sig.items():
@@ -338,7 +340,18 @@ class Batch:
         ms = (ctypes.c_double * 3)()
         _call("enomr_batch_info", self.handle, ctypes.cast(ctypes.byref(tf), _vp), ctypes.cast(ctypes.byref(nb), _vp),
               ctypes.cast(ms, _vp))
-        return {"tile_faces": tf.value, "workgroups": nb.value, "tune_ms": list(ms)}
+        tf2 = ctypes.c_int32()
+        tl2 = ctypes.c_int32()
+        ms2 = (ctypes.c_double * 3)()
+        _call("enomr_batch_info2d", self.handle, ctypes.cast(ctypes.byref(tf2), _vp),
+              ctypes.cast(ctypes.byref(tl2), _vp), ctypes.cast(ms2, _vp))
+        return {"tile_faces": tf.value, "workgroups": nb.value, "tune_ms": list(ms),
+                "tile2d": (tf2.value, tl2.value), "tune2d_ms": list(ms2)}
+
+    def set_tile2d(self, tile_faces, tile_lines):
+        """Use the 2D kernel's tile shape tile_faces x tile_lines (64x4, 32x8 or 16x16)."""
+        self.ctx._sync_stream()
+        _call("enomr_batch_set_tile2d", self.handle, int(tile_faces), int(tile_lines))
 
     def close(self):
         if self.handle:

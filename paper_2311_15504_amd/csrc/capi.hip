@@ -41,6 +41,8 @@ struct enomr_batch {
     int tf = 128;                  // faces per tile of the 1D kernel (autotuned)
     unsigned nblocks = 0;          // persistent workgroups of the 1D kernel
     unsigned nblocks2 = 0;         // persistent workgroups of the 2D kernel
+    int shape2 = 1;                // the 2D kernel's tile shape: index into kB2Shapes (autotuned)
+    double tune2_ms[3] = {0, 0, 0};// one-step times of the 2D tile shapes
     BatchProb* d_probs = nullptr;
     int* d_order = nullptr;
     BatchProb2* d_probs2 = nullptr;
@@ -912,14 +914,33 @@ hipError_t launch_batch(enomr_batch* b, int tf, const BatchProb* probs, hipStrea
     return hipGetLastError();
 }
 
-unsigned batch_blocks2(int nprob)
+// Tile shapes of the batched 2D kernel (faces per line, lines).
+constexpr int kB2Shapes[3][2] = {{64, 4}, {32, 8}, {16, 16}};
+
+#define DISPATCH_SHAPE2(shape, ...)                                             \
+    switch (shape) {                                                            \
+    case 0: { constexpr int TF = 64, TL = 4; __VA_ARGS__; } break;              \
+    case 2: { constexpr int TF = 16, TL = 16; __VA_ARGS__; } break;             \
+    default: { constexpr int TF = 32, TL = 8; __VA_ARGS__; } break;             \
+    }
+
+hipError_t launch_batch2(const enomr_batch* b, int shape, unsigned nblocks, const BatchProb2* probs,
+                         hipStream_t st)
+{
+    DISPATCH_SHAPE2(shape, hipLaunchKernelGGL((k_batch_euler2d<TF, TL>), dim3(nblocks), dim3(kB2NT), 0, st, probs,
+                                              b->d_order2, b->nprob2, b->d_queue + 1, b->d_params,
+                                              b->ctx->status));
+    return hipGetLastError();
+}
+
+unsigned batch_blocks2(int shape, int nprob)
 {
     int per_cu = 0, ncu = 0, dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_euler2d, kB2TF * kB2TL, 0) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
+    hipError_t e = hipErrorInvalidValue;
+    DISPATCH_SHAPE2(shape, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_euler2d<TF, TL>, kB2NT, 0));
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
     if (ncu < 1) ncu = 1;
     long nb = (long)per_cu * ncu;
     if (nb > nprob) nb = nprob;
@@ -961,6 +982,40 @@ void batch_free(enomr_batch* b)
 }
 
 }  // namespace
+
+// Capture the persistent launches into a graph, replayed by every advance
+// (replacing a previous one).  With both kinds of problems the 2D kernel runs
+// beside the 1D one: the second stream forks from the capture stream before
+// either launch.  Streams of default priority.
+enomr_status capture_batch(enomr_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    const int n1 = b->nprob, n2 = b->nprob2;
+    b->nblocks2 = n2 > 0 ? batch_blocks2(b->shape2, n2) : 0;
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(ENOMR_EHIP, "cannot begin capture");
+    hipError_t le = hipSuccess;
+    const bool both = n1 > 0 && n2 > 0;
+    hipStream_t s2 = both ? b->cap2 : b->cap;
+    if (both) {
+        if (le == hipSuccess) le = hipEventRecord(b->fork, b->cap);
+        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap2, b->fork, 0);
+    }
+    if (le == hipSuccess && n1 > 0) le = launch_batch(b, b->tf, b->d_probs, b->cap);
+    if (le == hipSuccess && n2 > 0) le = launch_batch2(b, b->shape2, b->nblocks2, b->d_probs2, s2);
+    if (both) {
+        if (le == hipSuccess) le = hipEventRecord(b->join, b->cap2);
+        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap, b->join, 0);
+    }
+    hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
+    if (le != hipSuccess || ce != hipSuccess) return fail(ENOMR_EHIP, "capture of the batch launch failed");
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+        return fail(ENOMR_EHIP, "cannot instantiate the batch graph");
+    return ENOMR_OK;
+}
 
 enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_problem* probs, double* const* U,
                                 int autotune, enomr_batch** out)
@@ -1067,7 +1122,6 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
         if (hipMemcpy(b->d_probs2, hp2.data(), sizeof(BatchProb2) * b->nprob2, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(b->d_order2, order2.data(), sizeof(int) * b->nprob2, hipMemcpyHostToDevice) != hipSuccess)
             return bail(ENOMR_EHIP, "cannot upload batch descriptors");
-        b->nblocks2 = batch_blocks2(b->nprob2);
     }
 
     // Autotune the 1D kernel's tile width: one step of the 1D problems on
@@ -1121,39 +1175,79 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
     }
     if (n1 > 0) b->nblocks = batch_blocks(b->tf, n1);
 
-    // Capture the persistent launches into a graph, replayed by every advance.
-    // With both kinds of problems the 2D kernel runs beside the 1D one: the
-    // second stream forks from the capture stream before either launch.
+    // Autotune the 2D kernel's tile shape the same way: one step of the 2D
+    // problems on scratch copies of their states, per shape.
+    const int n2 = b->nprob2;
+    b->shape2 = 1;
+    if (autotune == 1 && n2 > 0) {
+        size_t state_bytes = 0;
+        for (int k = 0; k < n2; ++k)
+            state_bytes += align_up(sizeof(double) * 4 * (size_t)probs[i2[k]].nx * (size_t)probs[i2[k]].ny);
+        double* scratch = nullptr;
+        BatchProb2* d_tune = nullptr;
+        if (hipMalloc(&scratch, state_bytes) != hipSuccess || hipMalloc(&d_tune, sizeof(BatchProb2) * n2) != hipSuccess) {
+            (void)hipFree(scratch);
+            return bail(ENOMR_ENOMEM, "cannot allocate autotune scratch");
+        }
+        std::vector<BatchProb2> tp = hp2;
+        size_t so = 0;
+        for (int k = 0; k < n2; ++k) {
+            tp[k].U = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) + so);
+            so += align_up(sizeof(double) * 4 * (size_t)probs[i2[k]].nx * (size_t)probs[i2[k]].ny);
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool ok = hipMemcpy(d_tune, tp.data(), sizeof(BatchProb2) * n2, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+        double best = 1e300;
+        for (int t = 0; ok && t < 3; ++t) {
+            for (int k = 0; k < n2 && ok; ++k)
+                ok = hipMemcpyAsync(tp[k].U, U[i2[k]],
+                                    sizeof(double) * 4 * (size_t)probs[i2[k]].nx * (size_t)probs[i2[k]].ny,
+                                    hipMemcpyDeviceToDevice, ctx->stream) == hipSuccess;
+            hipLaunchKernelGGL(k_set_batch_params, dim3(1), dim3(64), 0, ctx->stream, b->d_params, 0.5, 1L, b->d_queue);
+            ok = ok && hipEventRecord(e0, ctx->stream) == hipSuccess;
+            ok = ok && launch_batch2(b, t, batch_blocks2(t, n2), d_tune, ctx->stream) == hipSuccess;
+            ok = ok && hipEventRecord(e1, ctx->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.0f;
+            ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            b->tune2_ms[t] = ms;
+            if (ok && ms < best) {
+                best = ms;
+                b->shape2 = t;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(d_tune);
+        (void)hipFree(scratch);
+        if (!ok) return bail(ENOMR_EHIP, "autotune failed");
+    }
+
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)
         return bail(ENOMR_EHIP, "cannot create capture streams");
-    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return bail(ENOMR_EHIP, "cannot begin capture");
-    hipError_t le = hipSuccess;
-    const bool both = n1 > 0 && b->nprob2 > 0;
-    hipStream_t s2 = both ? b->cap2 : b->cap;
-    if (both) {
-        if (le == hipSuccess) le = hipEventRecord(b->fork, b->cap);
-        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap2, b->fork, 0);
+    if (enomr_status st = capture_batch(b)) {
+        batch_free(b);
+        return st;
     }
-    if (le == hipSuccess && n1 > 0) le = launch_batch(b, b->tf, b->d_probs, b->cap);
-    if (le == hipSuccess && b->nprob2 > 0) {
-        hipLaunchKernelGGL(k_batch_euler2d, dim3(b->nblocks2), dim3(kB2TF * kB2TL), 0, s2, b->d_probs2, b->d_order2,
-                           b->nprob2, b->d_queue + 1, b->d_params, ctx->status);
-        le = hipGetLastError();
-    }
-    if (both) {
-        if (le == hipSuccess) le = hipEventRecord(b->join, b->cap2);
-        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap, b->join, 0);
-    }
-    hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
-    if (le != hipSuccess || ce != hipSuccess) return bail(ENOMR_EHIP, "capture of the batch launch failed");
-    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
-        return bail(ENOMR_EHIP, "cannot instantiate the batch graph");
     *out = b;
     return ENOMR_OK;
+}
+
+enomr_status enomr_batch_set_tile2d(enomr_batch* b, int32_t tile_faces, int32_t tile_lines)
+{
+    if (!b) return fail(ENOMR_EINVAL, "batch is NULL");
+    if (enomr_status st = check_ctx(b->ctx)) return st;
+    int shape = -1;
+    for (int t = 0; t < 3; ++t)
+        if (kB2Shapes[t][0] == tile_faces && kB2Shapes[t][1] == tile_lines) shape = t;
+    if (shape < 0) return fail(ENOMR_EINVAL, "2D tile shape must be 64x4, 32x8 or 16x16");
+    // let replays of the current graph finish before it is replaced
+    HIP_TRY(hipStreamSynchronize(b->ctx->stream));
+    b->shape2 = shape;
+    return capture_batch(b);
 }
 
 enomr_status enomr_batch_advance(enomr_batch* b, double cfl, int64_t nsteps)
@@ -1165,6 +1259,16 @@ enomr_status enomr_batch_advance(enomr_batch* b, double cfl, int64_t nsteps)
                        b->d_queue);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipGraphLaunch(b->exec, b->ctx->stream));
+    return ENOMR_OK;
+}
+
+enomr_status enomr_batch_info2d(const enomr_batch* b, int32_t* tile_faces, int32_t* tile_lines, double* tune_ms)
+{
+    if (!b) return fail(ENOMR_EINVAL, "batch is NULL");
+    if (tile_faces) *tile_faces = kB2Shapes[b->shape2][0];
+    if (tile_lines) *tile_lines = kB2Shapes[b->shape2][1];
+    if (tune_ms)
+        for (int i = 0; i < 3; ++i) tune_ms[i] = b->tune2_ms[i];
     return ENOMR_OK;
 }
 

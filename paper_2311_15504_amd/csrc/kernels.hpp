@@ -1349,13 +1349,24 @@ __device__ __forceinline__ void block_line_speeds_2d(const double* __restrict__ 
     }
 }
 
-constexpr int kB2TF = 64, kB2TL = 4, kB2NCL = kB2TF + 17;   // the single-problem 2D tile shape
+// Tile shapes of the batched 2D kernel (faces per line x lines, 256 threads):
+// the batch's autotuner picks one.  Small problems leave lanes of long tiles
+// idle at the line ends; short tiles stage more halo per face.
+constexpr int kB2NT = 256;
 
-template <int R>
+template <int TF, int TL>
+struct B2Shape {
+    static_assert(TF * TL == kB2NT, "four waves per workgroup");
+    static constexpr int NCL = TF + 17;   // LDS stride per line: the order-17 window
+    using Lds = SweepLds<4, NCL * TL, TF * TL>;
+};
+
+template <int R, int TF, int TL>
 __device__ __forceinline__ void run_problem_2d(const BatchProb2& P, const BatchParams& prm, unsigned* status,
                                                char* lds_raw, double* red, double* s_dt)
 {
-    using Lds = SweepLds<4, kB2NCL * kB2TL, kB2TF * kB2TL>;
+    using Lds = typename B2Shape<TF, TL>::Lds;
+    constexpr int kB2TF = TF, kB2TL = TL, kB2NCL = B2Shape<TF, TL>::NCL;
     Lds& sm = *reinterpret_cast<Lds*>(lds_raw);
     const long nx = P.nx, ny = P.ny;
     for (long step = 0; step < prm.nsteps; ++step) {
@@ -1426,12 +1437,12 @@ __device__ __forceinline__ void run_problem_2d(const BatchProb2& P, const BatchP
 // Two workgroups per CU: the kernel holds every order's sweeps behind one
 // switch, and at four per CU it spilled about 300 VGPRs to scratch (measured
 // 15% slower on the batched 2D workload).
-__global__ __launch_bounds__(kB2TF * kB2TL, 2) void k_batch_euler2d(const BatchProb2* __restrict__ probs,
-                                                                     const int* __restrict__ order, int nprob,
-                                                                     int* queue, const BatchParams* prm,
-                                                                     unsigned* status)
+template <int TF, int TL>
+__global__ __launch_bounds__(kB2NT, 2) void k_batch_euler2d(const BatchProb2* __restrict__ probs,
+                                                            const int* __restrict__ order, int nprob, int* queue,
+                                                            const BatchParams* prm, unsigned* status)
 {
-    __shared__ __align__(16) char lds_raw[sizeof(SweepLds<4, kB2NCL * kB2TL, kB2TF * kB2TL>)];
+    __shared__ __align__(16) char lds_raw[sizeof(typename B2Shape<TF, TL>::Lds)];
     __shared__ double red[8];
     __shared__ double s_dt;
     __shared__ int s_k;
@@ -1444,13 +1455,13 @@ __global__ __launch_bounds__(kB2TF * kB2TL, 2) void k_batch_euler2d(const BatchP
         if (k >= nprob) return;   // the whole workgroup leaves together
         const BatchProb2 pr = probs[order[k]];
         switch (pr.R) {
-        case 3: run_problem_2d<3>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 4: run_problem_2d<4>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 5: run_problem_2d<5>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 6: run_problem_2d<6>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 7: run_problem_2d<7>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 8: run_problem_2d<8>(pr, P, status, lds_raw, red, &s_dt); break;
-        default: run_problem_2d<9>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 3: run_problem_2d<3, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 4: run_problem_2d<4, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 5: run_problem_2d<5, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 6: run_problem_2d<6, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 7: run_problem_2d<7, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
+        case 8: run_problem_2d<8, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
+        default: run_problem_2d<9, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
         }
     }
 }

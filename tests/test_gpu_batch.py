@@ -180,3 +180,43 @@ def test_batch_reports_a_problem_the_method_drives_non_physical(ctx):
         ctx.check()
         assert torch.equal(U, states[k])
     batch.close()
+
+
+@pytest.mark.parametrize("shape", [(64, 4), (32, 8), (16, 16)])
+def test_batch_2d_every_tile_shape_equals_single_problem_runs(ctx, shape):
+    # The 2D kernel's tile shapes partition the faces differently; every face
+    # is computed the same way, so each shape gives the single-problem result.
+    import torch
+    import paper_2311_15504_amd as enomr
+    probs, data = _problems_2d(7, 5)
+    states = [torch.from_numpy(U).cuda() for U in data]
+    batch = enomr.Batch(ctx, probs, states, autotune=False)
+    assert batch.info()["tile2d"] == (32, 8)
+    batch.set_tile2d(*shape)
+    assert batch.info()["tile2d"] == shape
+    batch.advance(0.5, 3)
+    ctx.check()
+    for p, U0, Ub in zip(probs, data, states):
+        Us = torch.from_numpy(U0).cuda()
+        ctx.advance(p, Us, 0.5, 3)
+        ctx.check()
+        assert torch.equal(Ub, Us), (shape, p.nx, p.ny, p.order)
+    with pytest.raises(enomr.EnomrError):
+        batch.set_tile2d(48, 4)
+    batch.close()
+
+
+def test_batch_2d_autotune_times_every_shape(ctx):
+    import torch
+    import paper_2311_15504_amd as enomr
+    probs, data = _problems_2d(6, 8)
+    states = [torch.from_numpy(U).cuda() for U in data]
+    batch = enomr.Batch(ctx, probs, states, autotune=True)
+    info = batch.info()
+    assert all(t > 0 for t in info["tune2d_ms"])
+    k = [(64, 4), (32, 8), (16, 16)].index(info["tile2d"])
+    assert info["tune2d_ms"][k] == min(info["tune2d_ms"])
+    # the tuning steps ran on copies: the states are untouched until advance
+    for U0, Ub in zip(data, states):
+        assert torch.equal(Ub, torch.from_numpy(U0).cuda())
+    batch.close()
