@@ -264,6 +264,32 @@ def test_euler2d_full_size_sampled(ctx):
     ctx.check()
 
 
+def test_euler2d_full_size_mass_scaling_is_bitwise(ctx):
+    # The 2048^2, 17th-order workload in the benchmark's launch configuration:
+    # one SSP-RK3 step of 16 U is 16 times the step of U bit for bit, with the
+    # same dt and the same stencils at every face of every stage (the
+    # selection is invariant under scaling; 16 = 4^2 also scales the Roe
+    # weights exactly).
+    import paper_2311_15504_amd as enomr
+    import torch
+    n = 2048
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(0, n, n)
+    prob = enomr.Problem.euler2d(n, n, hx, hy, 17)
+    ib = prob.idx_bytes()
+    out = []
+    for lam in (1.0, 16.0):
+        U = _dev(lam * U0)
+        log = torch.empty(3 * ib, dtype=torch.uint8, device="cuda")
+        dt = ctx.dt(prob, U, 0.5)
+        ctx.ssprk3_step(prob, U, dt, log)
+        ctx.check()
+        out.append((U, log, _host(dt)[0]))
+    (A, la, da), (B, lb, db) = out
+    assert da == db
+    assert torch.equal(la, lb)
+    assert torch.equal(B, 16.0 * A)
+
+
 # ---------------------------------------------------------------------------
 # dt, status, determinism
 # ---------------------------------------------------------------------------

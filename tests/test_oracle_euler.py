@@ -95,6 +95,34 @@ def test_y_invariant_2d_equals_1d_bitwise():
             assert np.all(L2[2, y] == 0.0)
 
 
+@pytest.mark.parametrize("lam", [4.0, 1.0 / 16.0, 2.0 ** 40])
+def test_mass_scaling_by_powers_of_four_is_bitwise(lam):
+    # Scaling rho, the momenta and E by lam = 4^k keeps u, v, p/rho, c, H
+    # and alpha exactly, scales p, F, G+- and every projected value by lam
+    # exactly, and scales the Roe weights sqrt(rho) by 2^k exactly, so the
+    # Roe state and eigenvectors are unchanged.  Every IS and IS0 scales by
+    # lam, so every stencil choice is the same and L(lam U) = lam L(U) bit
+    # for bit (Sec. 4.2: the selection is invariant under scaling of the
+    # data).  Any term of the wrong degree in the scaled variables breaks it:
+    # a sound speed from p instead of p/rho, an additive constant in a
+    # weight, an unscaled threshold in a comparison.
+    _, h, U1 = workloads.euler1d_riemann_perturbed(3, 120)
+    _, U2 = workloads.euler2d_quadrants_vortices(4, 40, 36, nvort=3)
+    for order in (5, 9, 17):
+        L, idx, a = oracle.euler1d_rhs(order, U1, h, G, oracle.OUTFLOW, with_idx=True)
+        Ls, idxs, a_s = oracle.euler1d_rhs(order, lam * U1, h, G, oracle.OUTFLOW, with_idx=True)
+        assert np.array_equal(Ls, lam * L)
+        assert np.array_equal(idxs, idx) and a_s == a
+        L = oracle.euler2d_rhs(order, U2, 0.05, 0.055, G, oracle.PERIODIC, oracle.OUTFLOW)
+        Ls = oracle.euler2d_rhs(order, lam * U2, 0.05, 0.055, G, oracle.PERIODIC, oracle.OUTFLOW)
+        assert np.array_equal(Ls, lam * L)
+    # An odd power of two rounds the Roe weights differently, and choices at
+    # rounding-level ties (flat fields) flip: there it is not an identity.
+    L = oracle.euler2d_rhs(17, U2, 0.05, 0.055, G, oracle.PERIODIC, oracle.OUTFLOW)
+    Ls = oracle.euler2d_rhs(17, 2.0 * U2, 0.05, 0.055, G, oracle.PERIODIC, oracle.OUTFLOW)
+    assert not np.array_equal(Ls, 2.0 * L)
+
+
 def test_transposed_problem_gives_transposed_residual_bitwise():
     _, U = workloads.euler2d_quadrants_vortices(11, 36, 36, nvort=3)
     UT = np.stack([U[0].T, U[2].T, U[1].T, U[3].T]).copy()
