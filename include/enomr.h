@@ -58,7 +58,9 @@ enum { ENOMR_ALPHA_LINE = 0, ENOMR_ALPHA_FIELD = 1 };
  *            ENOMR_BURGERS (u_t + (u^2/2)_x = 0, nvar 1, ndim 1),
  *            ENOMR_EULER (nvar 3 in 1D: rho, rho u, E; nvar 4 in 2D:
  *            rho, rho u, rho v, E; ideal gas with ratio gamma).
- *   nx, ny   interior nodes per axis (ny = 1 in 1D); at least 2r+1 each.
+ *   nx, ny   interior nodes per axis (ny = 1 in 1D); at least 2r+1 and at
+ *            most 2^31 each; in 2D also ny <= 2097120 and nx*ny <= 2^32
+ *            (ENOMR_EINVAL otherwise).
  *   hx, hy   node spacing.
  *   order    2r-1, odd in 5..17.
  *   bc_x/y   ENOMR_PERIODIC or ENOMR_OUTFLOW (zero-gradient copy).
@@ -123,7 +125,7 @@ enomr_status enomr_coefficients(int order, int32_t *ncand, int32_t *mn, double *
  * f_with_halo: n + 2r - 1 values; face i lies between array entries i+r-1 and
  * i+r.  sign = +1 reconstructs f^+ (centred on the left cell), -1 reconstructs
  * f^- (the mirror image, centred on the right cell).  fhat: n values.
- * idx (nullable): n bytes.
+ * idx (nullable): n bytes.  0 <= n <= 2^38 (ENOMR_EINVAL otherwise).
  */
 enomr_status enomr_recon_faces(enomr_ctx *ctx, int order, int sign, int64_t n,
                                const double *f_with_halo, double *fhat, uint8_t *idx);

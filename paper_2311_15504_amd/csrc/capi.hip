@@ -105,6 +105,11 @@ enomr_status check_problem(const enomr_problem* p)
     if (p->system != ENOMR_EULER && p->split != ENOMR_SPLIT_LF && p->split != ENOMR_SPLIT_NONE)
         return fail(ENOMR_EINVAL, "unknown split");
     if (p->nx > (1L << 31) || p->ny > (1L << 31)) return fail(ENOMR_EINVAL, "grid too large");
+    // 2D launch shapes: the alpha pass has ceil(ny/32) rows of workgroups (at
+    // most 65535), and the sweeps' workgroup counts stay below 2^32 for
+    // nx*ny <= 2^32 cells
+    if (p->ndim == 2 && (p->ny > 65535L * 32 || p->nx * p->ny > (1L << 32)))
+        return fail(ENOMR_EINVAL, "2D grid too large (ny <= 2097120, nx*ny <= 2^32)");
     if (p->recon != ENOMR_CHARACTERISTIC && p->recon != ENOMR_COMPONENTWISE)
         return fail(ENOMR_EINVAL, "unknown recon");
     if (p->alpha_mode != ENOMR_ALPHA_LINE && p->alpha_mode != ENOMR_ALPHA_FIELD)
@@ -607,6 +612,7 @@ enomr_status enomr_recon_faces(enomr_ctx* ctx, int order, int sign, int64_t n, c
     if (!order_ok(order)) return fail(ENOMR_EORDER, "order must be odd in 5..17");
     if (sign != 1 && sign != -1) return fail(ENOMR_EINVAL, "sign must be +1 or -1");
     if (n < 0 || (n > 0 && (!f_with_halo || !fhat))) return fail(ENOMR_EINVAL, "bad arrays");
+    if (n > (int64_t(1) << 38)) return fail(ENOMR_EINVAL, "n too large (at most 2^38 faces)");   // grid < 2^32 blocks
     if (n == 0) return ENOMR_OK;
     const unsigned nb = blocks_for(n, 256);
     if (sign > 0) {

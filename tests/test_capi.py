@@ -82,6 +82,13 @@ def test_bad_arguments_are_rejected_without_a_gpu():
     assert e.value.status == 1
     prob = enomr.Problem.euler2d(2048, 2048, 1 / 1024, 1 / 1024, 17)
     assert enomr.workspace_size(prob) >= 3 * 4 * 2048 * 2048 * 8
+    # 2D size limits of the launch shapes: rejected before anything is launched
+    for nx, ny in ((64, 65535 * 32 + 1), (1 << 17, 1 << 16)):
+        with pytest.raises(enomr.EnomrError) as e:
+            enomr.workspace_size(enomr.Problem.euler2d(nx, ny, 0.1, 0.1, 17))
+        assert e.value.status == 1
+    assert enomr.workspace_size(enomr.Problem.euler2d(64, 65535 * 32, 0.1, 0.1, 17)) > 0
+    assert enomr.workspace_size(enomr.Problem.euler2d(1 << 16, 1 << 16, 0.1, 0.1, 17)) > 0
 
 
 def test_problem_struct_layout_matches_the_header(tmp_path):
