@@ -141,6 +141,38 @@ def test_batch_matches_oracle(ctx):
     batch.close()
 
 
+def test_batch_full_workload_sampled(ctx):
+    # The batched workload at its full size: 4096 problems, N ~ U{256..16384},
+    # orders {7, 9, 13, 17}, 100 steps in one graph launch with the autotuned
+    # tile width.  A seeded sample (with the longest and the shortest problem)
+    # equals its single-problem runs bit for bit, and the three shortest of the
+    # sample equal the oracle to the final-time tolerance.
+    import torch
+    import paper_2311_15504_amd as enomr
+    nsteps = 100
+    plist = workloads.batched_problems(0, nprob=4096)
+    probs = [enomr.Problem.euler1d(p["n"], p["h"], p["order"]) for p in plist]
+    states = [torch.from_numpy(p["U"]).cuda() for p in plist]
+    print("case: batch of %d 1D Euler problems, %d steps" % (len(plist), nsteps), flush=True)
+    batch = enomr.Batch(ctx, probs, states, autotune=True)
+    batch.advance(0.5, nsteps)
+    ctx.check()
+    ns = np.array([p["n"] for p in plist])
+    rng = np.random.default_rng(17)
+    sample = sorted(set(rng.choice(len(plist), 10, replace=False).tolist()) | {int(ns.argmax()), int(ns.argmin())})
+    for i in sample:
+        U = torch.from_numpy(plist[i]["U"]).cuda()
+        ctx.advance(probs[i], U, 0.5, nsteps)
+        ctx.check()
+        assert torch.equal(U, states[i]), (i, plist[i]["n"], plist[i]["order"])
+    for i in sorted(sample, key=lambda k: ns[k])[:3]:
+        p = plist[i]
+        ref, _ = oracle.euler1d_run(p["order"], p["U"], p["h"], nsteps, cfl=0.5)
+        got = states[i].cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max()), (i, p["n"], p["order"])
+    batch.close()
+
+
 def test_batch_rejects_bad_problems(ctx):
     import torch
     import paper_2311_15504_amd as enomr

@@ -168,6 +168,27 @@ def test_euler1d_run_matches_oracle(ctx):
     assert np.abs(got - ref).max() <= FINAL_TOL * max(1.0, np.abs(ref).max())
 
 
+def test_euler1d_full_config_run_matches_oracle(ctx):
+    # The 1D Euler workload at its full size: N = 4096, 9th order, 1000 steps
+    # at CFL 0.5 (the oracle takes some 25 s).  Every step's dt equals the
+    # oracle's bit for bit, and the final state is within the final-time
+    # tolerance.
+    import paper_2311_15504_amd as enomr
+    import torch
+    n, order, nsteps = 4096, 9, 1000
+    _, h, U0 = workloads.euler1d_riemann_perturbed(0, n)
+    print("case: 1D Euler N=%d order %d, %d steps" % (n, order, nsteps), flush=True)
+    prob = enomr.Problem.euler1d(n, h, order)
+    U = _dev(U0)
+    dt_log = torch.zeros(nsteps, dtype=torch.float64, device="cuda")
+    ctx.advance(prob, U, 0.5, nsteps, dt_log=dt_log)
+    ctx.check()
+    got, dts_gpu = _host(U), _host(dt_log)
+    ref, dts = oracle.euler1d_run(order, U0, h, nsteps, cfl=0.5)
+    assert np.array_equal(dts_gpu, np.array(dts))
+    assert np.abs(got - ref).max() <= FINAL_TOL * max(1.0, np.abs(ref).max())
+
+
 # ---------------------------------------------------------------------------
 # Euler 2D
 # ---------------------------------------------------------------------------
