@@ -125,6 +125,31 @@ def test_batch_2d_problems_equal_single_problem_runs_bitwise(ctx, with_1d):
     batch.close()
 
 
+def test_batch_graph_replays_each_match_eager_runs(ctx):
+    # The batch is one captured graph replayed per advance call.  Four replays
+    # with eager launches and synchronisations between them: after every
+    # replay each problem (1D and 2D together) equals its eager single-problem
+    # run bit for bit.
+    import torch
+    import paper_2311_15504_amd as enomr
+    p1, d1 = _problems(7, 6)
+    p2, d2 = _problems_2d(5, 7)
+    probs, data = p1 + p2, d1 + d2
+    states = [torch.from_numpy(U).cuda() for U in data]
+    refs = [torch.from_numpy(U).cuda() for U in data]
+    batch = enomr.Batch(ctx, probs, states, autotune=False)
+    for replay in range(4):
+        batch.advance(0.5, 2)
+        ctx.check()
+        for p, U in zip(probs, refs):
+            ctx.advance(p, U, 0.5, 2)
+        ctx.check()
+        torch.cuda.synchronize()
+        for k, (Ub, Ur) in enumerate(zip(states, refs)):
+            assert torch.equal(Ub, Ur), (replay, k, probs[k].ndim, probs[k].nx, probs[k].order)
+    batch.close()
+
+
 def test_batch_matches_oracle(ctx):
     import torch
     import paper_2311_15504_amd as enomr
