@@ -313,8 +313,10 @@ class Batch:
     the batch and are advanced in place."""
 
     def __init__(self, ctx, problems, states, autotune=True, tile_faces=None):
-        """autotune: time the tile widths 64/128/256 and keep the fastest;
-        tile_faces: use that width instead (autotune is then ignored)."""
+        """autotune: time one step per 1D tile width (64/128/256) and per 2D
+        tile shape (64x4, 32x8, 16x16 faces x lines) on scratch copies and
+        keep the fastest of each; tile_faces: use that 1D width instead
+        (autotune is then ignored; set_tile2d() picks a 2D shape)."""
         if len(problems) != len(states) or not problems:
             raise ValueError("one state per problem")
         for p, U in zip(problems, states):
