@@ -338,6 +338,45 @@ def test_nonphysical_state_is_reported(ctx):
     ctx.check()                                         # cleared
 
 
+def test_calls_follow_the_current_torch_stream(ctx):
+    # The binding issues library work on torch's current stream: on a side
+    # stream (default priority), torch work queued before and after the call
+    # on that stream is ordered with it, and the result equals the run on the
+    # default stream bit for bit.
+    import paper_2311_15504_amd as enomr
+    import torch
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(12, 200, 150)
+    prob = enomr.Problem.euler2d(200, 150, hx, hy, 13)
+    ref = _dev(U0)
+    ctx.advance(prob, ref, 0.5, 3)
+    ctx.check()
+    src = _dev(U0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        U = src * 1.0                      # produced on the side stream
+        ctx.advance(prob, U, 0.5, 3)
+        V = U * 1.0                        # consumed on the side stream
+    side.synchronize()
+    ctx.check()
+    assert torch.equal(V, ref)
+
+
+def test_profile_counts_every_launch_class(ctx):
+    import paper_2311_15504_amd as enomr
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(13, 128, 96)
+    prob = enomr.Problem.euler2d(128, 96, hx, hy, 9)
+    U = _dev(U0)
+    ctx.profile_start()
+    ctx.advance(prob, U, 0.5, 2)
+    prof = ctx.profile_stop()
+    ctx.check()
+    # per step: 3 stages of (alpha, y sweep, x sweep) and one dt
+    assert prof["sweep_x"][1] == 6 and prof["sweep_y"][1] == 6
+    assert prof["aux"][1] >= 8
+    assert all(v[0] > 0.0 for v in prof.values() if v[1] > 0)
+
+
 def test_runs_are_deterministic(ctx):
     import paper_2311_15504_amd as enomr
     (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(9, 256, 256)
