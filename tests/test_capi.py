@@ -91,6 +91,32 @@ def test_bad_arguments_are_rejected_without_a_gpu():
     assert enomr.workspace_size(enomr.Problem.euler2d(1 << 16, 1 << 16, 0.1, 0.1, 17)) > 0
 
 
+def test_last_error_is_per_thread():
+    # enomr_last_error() is thread-local: two threads that fail differently
+    # each read their own message.
+    import threading
+    lib = enomr.lib()
+    bad_order = enomr.Problem.euler2d(64, 64, 0.1, 0.1, 19)
+    bad_size = enomr.Problem.euler2d(10, 64, 0.1, 0.1, 17)
+    size = ctypes.c_size_t()
+    go = threading.Barrier(2)
+    got = {}
+
+    def run(name, prob):
+        st = lib.enomr_workspace_size(ctypes.byref(prob), ctypes.byref(size))
+        go.wait()                      # both have failed before either reads
+        got[name] = (st, lib.enomr_last_error().decode())
+
+    ts = [threading.Thread(target=run, args=("order", bad_order)),
+          threading.Thread(target=run, args=("size", bad_size))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert got["order"][0] == 2 and "order" in got["order"][1]
+    assert got["size"][0] == 1 and "nx" in got["size"][1]
+
+
 def test_problem_struct_layout_matches_the_header(tmp_path):
     # offsets and size of enomr_problem as the C compiler lays it out
     fields = [f for f, _ in enomr.Problem._fields_]
