@@ -210,6 +210,36 @@ def test_euler2d_operator(ctx, order):
     assert np.array_equal(_host(got), ref)
 
 
+@pytest.mark.parametrize("order", [5, 17])
+def test_degenerate_flat_and_single_jump_states(ctx, order):
+    # The method's degenerate cases: a uniform state, where every window is
+    # flat (IS0 = 0, so no indicator can pass and each face takes the centre
+    # value), and a single contact in an otherwise uniform state (flat faces,
+    # faces whose windows straddle the jump, smooth faces none).  Stencil logs
+    # and L bitwise equal to the oracle's; the uniform state's L is exactly 0.
+    import paper_2311_15504_amd as enomr
+    nx, ny = 90, 70
+    hx = hy = 2.0 / nx
+    rho = np.full((ny, nx), 0.8)
+    uniform = workloads.conserved_2d(rho, np.full_like(rho, 0.3), np.full_like(rho, -0.2), np.full_like(rho, 1.1))
+    rho_c = rho.copy()
+    rho_c[:, nx // 3:] = 0.35                               # contact: u, v, p continuous
+    contact = workloads.conserved_2d(rho_c, np.full_like(rho, 0.3), np.full_like(rho, -0.2), np.full_like(rho, 1.1))
+    for name, U in (("uniform", uniform), ("contact", contact)):
+        for bcx, bcy in ((enomr.PERIODIC, enomr.OUTFLOW), (enomr.OUTFLOW, enomr.PERIODIC)):
+            ref, ix, iy, _, _ = oracle.euler2d_rhs(order, U, hx, hy, bcx=bcx, bcy=bcy, with_idx=True)
+            prob = enomr.Problem.euler2d(nx, ny, hx, hy, order, bcx, bcy)
+            got, gidx = ctx.rhs(prob, _dev(U), with_idx=True)
+            ctx.check()
+            gidx = _host(gidx)
+            nxf = ny * (nx + 1) * 8
+            assert np.array_equal(gidx[:nxf].reshape(ny, nx + 1, 4, 2), ix), (name, bcx)
+            assert np.array_equal(gidx[nxf:].reshape(ny + 1, nx, 4, 2), iy), (name, bcx)
+            assert np.array_equal(_host(got), ref), (name, bcx)
+            if name == "uniform":
+                assert not np.any(_host(got)), "uniform state must have L = 0 exactly"
+
+
 def test_euler2d_riemann_configurations(ctx):
     import paper_2311_15504_amd as enomr
     for cfg in (1, 2):
