@@ -1,7 +1,7 @@
 """Write the paper's printed coefficient and convergence tables as text fixtures.
 
-Reads the LaTeX source of the paper (H. Shen, arXiv 2311.15504) from
-/root/reference/PAPER.md and writes, next to this script:
+Reads the LaTeX source of the paper (H. Shen, arXiv 2311.15504), whose path
+is the one command-line argument, and writes, next to this script:
 
 * a_coefficients.txt  - Tables Flux_reconstruction1/2 (a_l, Sec. 3.1)
 * b_coefficients.txt  - Tables ISCoe1/2 (b_l, Sec. 3.2)
@@ -9,14 +9,14 @@ Reads the LaTeX source of the paper (H. Shen, arXiv 2311.15504) from
   9th, 13th17th and 1DBurgersConvergence (Sec. 4.1, 4.2)
 
 Values are copied verbatim as printed (typos included); the tests decide what
-they mean.  Run once by hand: ``python tests/golden/extract_paper_tables.py``.
+they mean.  Run once by hand:
+``python tests/golden/extract_paper_tables.py <path of the paper's LaTeX source>``.
 Nothing at test time reads the paper.
 """
 import os
 import re
 import sys
 
-PAPER = "/root/reference/PAPER.md"
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 STENCIL_RE = re.compile(r"S_\{j(?:-(\d+))?\}\^\{j(?:\+(\d+))?\}")
@@ -90,9 +90,12 @@ def parse_convergence(lines, label, kind):
 
 
 def main():
-    if not os.path.exists(PAPER):
-        sys.exit("paper source not found at %s" % PAPER)
-    with open(PAPER) as fh:
+    if len(sys.argv) != 2:
+        sys.exit("usage: extract_paper_tables.py <path of the paper's LaTeX source>")
+    paper = sys.argv[1]
+    if not os.path.exists(paper):
+        sys.exit("paper source not found at %s" % paper)
+    with open(paper) as fh:
         lines = fh.read().splitlines()
 
     a_rows = parse_coeff_table(lines, "Table:Flux_reconstruction1") + \
