@@ -5,28 +5,30 @@
  * library is checked against.  Only the test suite, the smoke check and the
  * CPU-baseline leg of the benchmark may load it.  It shares no code, header or
  * table with the GPU library: the stencil coefficients arrive as arguments,
- * computed in exact rational arithmetic by oracle/coeffs.py.
+ * derived in exact rational arithmetic by oracle/coeffs.py.
  *
- * Everything is FP64.  Built with -ffp-contract=off: every operation is rounded
- * separately, except where fma() is written out.  The evaluation order of each
- * formula is part of the specification (the paper leaves it open); the GPU
- * kernels follow the same order so that stencil choices agree bit for bit.
- *
- *   - dot products (fluxes, the full stencil's IS, R w-hat): first term a
- *     plain product, then fma() terms, in ascending physical cell (or
- *     component) order;
- *   - projections L G: the same chain from the last component to the first
- *     (rows u-c and u+c then share their last two terms);
- *   - the full stencil of a characteristic field (candidate 0): its indicator
- *     and flux are the projection of the stencil sums of the split fluxes,
- *     l_k.(sum_l b_l G_l) and l_k.(sum_l a_l G_l), each component's sum in
- *     ascending cell order (the same values as sum_l b_l (l_k.G_l) in exact
- *     arithmetic, since the projection is linear);
- *   - IS of every other candidate: the (m+n)-th undivided difference of its
- *     cells in ascending order, by repeated differencing f_{i+1} - f_i;
- *   - IS0 second differences: (f_c - 2 f_{c-1}) + f_{c-2};
- *   - one reciprocal per cell (1/rho) and per face (1/(sqrt(rho_L)+sqrt(rho_R)))
- *     multiplies instead of repeated divisions.
+ * Every step follows the method in the order the paper states it, with each
+ * formula written the plain way:
+ *   - primitive variables by division (u = m / rho, H = (E + p) / rho,
+ *     c = sqrt(gamma p / rho));
+ *   - the Roe state with sqrt(rho) weights divided by their sum, and the
+ *     closed-form left and right eigenvectors of the face-normal Jacobian;
+ *   - every cell of a face's window projected onto every characteristic field
+ *     (l_k . G, a dot product over the conserved components in ascending
+ *     order), then the scalar reconstruction of Sec. 3.2 applied to each field
+ *     and sign on the projected values;
+ *   - every indicator IS = |sum_l b_l f_{j+l}| with the b_l of Tables ISCoe1/2
+ *     (Eq. ISCoe), every flux sum_l a_l f_{j+l} with the a_l of Tables
+ *     Flux_reconstruction1/2 (Eq. ReconstructedFlux), candidates tested in
+ *     list order until one passes (Step 3.1);
+ *   - dot products as fma() chains over ascending cells (or components);
+ *   - IS0 second differences as (f_c - 2 f_{c-1}) + f_{c-2}.
+ * Built with -ffp-contract=off, so apart from the written fma() calls every
+ * operation rounds on its own.  The paper fixes no floating-point order, so an
+ * implementation that evaluates in another order can decide a comparison
+ * differently where it lies within rounding of a tie.  The near-tie record
+ * (orc_ties) measures the margin mu of each such comparison and, if asked,
+ * takes the other implementation's choice where |mu| is below a tolerance.
  *
  * Method steps and where the paper states them:
  *   global Lax-Friedrichs splitting ............. Sec. 2.1, Eq. (LF_Flux_Split)
@@ -45,40 +47,130 @@
  *     scalar procedure applied to a system component by component);
  *   per-field alpha: each characteristic field k splits with its own
  *     alpha_k = max over the line of |lambda_k| (lambda = u-c, u, [u,] u+c),
- *     a field-wise reading of the maximum of Eq. (LF_Flux_Split);
- *     w+-_k = (l_k.F +- alpha_k l_k.U) / 2, each product l_k.x by the
- *     projection chain, then t = alpha_k (l_k.U), w+- = 0.5 (l_k.F +- t);
+ *     a field-wise reading of the maximum of Eq. (LF_Flux_Split):
+ *     w+-_k = (l_k.F +- t) / 2 with t = alpha_k (l_k.U);
  *   gravity: the source g [0, 0, rho, rho v] of the Rayleigh-Taylor problem
  *     (Sec. 4.4) added to the 2D right-hand side after the two sweeps.
+ *
+ * Compiled twice: in FP64 (everything), and with -DORC_QUAD in IEEE binary128
+ * (the scalar path only, names suffixed _q), the precision in which the paper
+ * ran its convergence tests (Sec. 4 preamble).  The 2D operator and 1D faces
+ * run in parallel over independent lines (faces) with OpenMP; every value is
+ * computed by the same operations whatever the thread count.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifdef ORC_QUAD
+#include <quadmath.h>
+typedef __float128 real;
+#define R_ABS(x) fabsq(x)
+#define R_MAX(a, b) fmaxq(a, b)
+#define R_MIN(a, b) fminq(a, b)
+/* at 113 significant bits the fusion of a product into a sum is immaterial */
+#define R_FMA(a, b, c) ((a) * (b) + (c))
+#define ORC_FN(name) name##_q
+#else
+typedef double real;
+#define R_ABS(x) fabs(x)
+#define R_MAX(a, b) fmax(a, b)
+#define R_MIN(a, b) fmin(a, b)
+#define R_FMA(a, b, c) fma(a, b, c)
+#define ORC_FN(name) name
+#endif
 
 /* ------------------------------------------------------------------------ */
-/* Operation counter                                                          */
+/* Operation counter (FP64 build)                                            */
 /* ------------------------------------------------------------------------ */
 
 /*
- * Algorithmic operation count of the Euler operator, taken as the method's
- * steps run (the early exit of Step 3.1 included): FP64 flops with fma = 2;
- * add, sub, mul, div, sqrt, min, max and compare = 1; |x|, negation and
- * products or sums with a structural 0 or 1 of the eigenvectors are free.
- * A shared subexpression counts once (the last two terms of the u-c and u+c
- * rows of L, E + p of a cell).  The indicators of the candidates after a
- * failed full stencil count as the cheaper of two ways to obtain them up to
- * the accepted candidate: one b_l chain per candidate scanned, or one
- * difference table of the window ((2r-2)(2r-1)/2 - 1 subtractions) with one
- * compare per candidate.  The wave speeds, alpha and dt (a separate step) and
- * the RK stage combination are not part of the operator count.
+ * Algorithmic operation count of the Euler operator and the SSP-RK3 stage
+ * combination, taken as the method's steps run: add, sub, mul, div, sqrt,
+ * fma, min, max and compare count 1 each; |x| and negation are free.  Only
+ * the candidates the paper's early exit reaches are counted (Step 3.1 stops
+ * at the first passing candidate), even where the oracle evaluates more of
+ * them to measure margins.  A value computed once and used twice counts once.
+ * Primitive variables and split fluxes count once per cell of a line (its
+ * ghost copies are not counted).  Per-line alphas and dt are not counted.
+ * Categories: x lines (1D lines), y lines, the 2D sum L_x + L_y, and the
+ * SSP-RK3 stage combination.
  */
-static double g_ops;
-static int g_counting;
+enum { ORC_OPS_X = 0, ORC_OPS_Y = 1, ORC_OPS_SUM = 2, ORC_OPS_RK = 3, ORC_OPS_NCAT = 4 };
 
-void orc_ops_begin(void) { g_ops = 0.0; g_counting = 1; }
-double orc_ops_end(void) { g_counting = 0; return g_ops; }
-#define OPS(n) do { if (g_counting) g_ops += (double)(n); } while (0)
+#ifndef ORC_QUAD
+static int g_count_on;
+static double g_ops[ORC_OPS_NCAT];
+static _Thread_local double t_ops[ORC_OPS_NCAT];
+static _Thread_local int t_cat, t_count;
+
+#define OPS(n) do { if (t_count && g_count_on) t_ops[t_cat] += (double)(n); } while (0)
+
+static void ops_enter(int cat)
+{
+    t_count = g_count_on;
+    t_cat = cat;
+}
+
+static void ops_off(void) { t_count = 0; }
+
+static void ops_flush(void)
+{
+    /* integer-valued partial sums: exact in any merge order */
+    for (int i = 0; i < ORC_OPS_NCAT; ++i) {
+        if (t_ops[i] != 0.0) {
+#pragma omp critical(orc_ops)
+            g_ops[i] += t_ops[i];
+            t_ops[i] = 0.0;
+        }
+    }
+}
+
+void orc_ops_begin(void)
+{
+    for (int i = 0; i < ORC_OPS_NCAT; ++i) g_ops[i] = 0.0;
+    g_count_on = 1;
+}
+
+/* Stops counting; the total, and per category into cats[4] (nullable). */
+double orc_ops_end(double *cats)
+{
+    g_count_on = 0;
+    double s = 0.0;
+    for (int i = 0; i < ORC_OPS_NCAT; ++i) {
+        if (cats) cats[i] = g_ops[i];
+        s += g_ops[i];
+    }
+    return s;
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+#else
+#define OPS(n) do { } while (0)
+static void ops_enter(int cat) { (void)cat; }
+static void ops_off(void) { }
+static void ops_flush(void) { }
+#endif
 
 #define ORC_MAXC 29
 #define ORC_MAXW 17
@@ -93,13 +185,20 @@ typedef struct {
     int r;
     int ncand;
     int m[ORC_MAXC], n[ORC_MAXC];
-    double a[ORC_MAXC][ORC_MAXW];   /* a[c][l+m], l = -m..n */
-    double b[ORC_MAXC][ORC_MAXW];   /* b[c][l+m] */
+    real a[ORC_MAXC][ORC_MAXW];   /* a[c][l+m], l = -m..n */
+    real b[ORC_MAXC][ORC_MAXW];   /* b[c][l+m] */
 } orc_table;
 
-orc_table *orc_table_new(int order, int ncand, const int *mn, const double *a, const double *b)
+/*
+ * A candidate table: mn holds (m, n) per candidate in list order; the a_l
+ * arrive as exact fractions anum/aden (each rounded here to the nearest value
+ * of the real type by one division of exactly representable integers), the
+ * b_l as integers.  Arrays hold ORC_MAXW entries per candidate, entry l+m.
+ */
+orc_table *ORC_FN(orc_table_new)(int order, int ncand, const int *mn, const int64_t *anum, const int64_t *aden,
+                                 const int64_t *bint)
 {
-    if (ncand < 1 || ncand > ORC_MAXC) return NULL;
+    if (ncand < 1 || ncand > ORC_MAXC || order < 5 || order > 17 || !(order & 1)) return NULL;
     orc_table *t = (orc_table *)calloc(1, sizeof(orc_table));
     if (!t) return NULL;
     t->order = order;
@@ -109,14 +208,36 @@ orc_table *orc_table_new(int order, int ncand, const int *mn, const double *a, c
         t->m[c] = mn[2 * c];
         t->n[c] = mn[2 * c + 1];
         for (int l = 0; l < ORC_MAXW; ++l) {
-            t->a[c][l] = a[c * ORC_MAXW + l];
-            t->b[c][l] = b[c * ORC_MAXW + l];
+            const int64_t d = aden[c * ORC_MAXW + l];
+            t->a[c][l] = d ? (real)anum[c * ORC_MAXW + l] / (real)d : (real)0;
+            t->b[c][l] = (real)bint[c * ORC_MAXW + l];
         }
     }
     return t;
 }
 
-void orc_table_free(orc_table *t) { free(t); }
+void ORC_FN(orc_table_free)(orc_table *t) { free(t); }
+
+/* ------------------------------------------------------------------------ */
+/* Near-tie record (FP64 build)                                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * follow: another implementation's stencil log for the same call (the layout
+ * of the call's own log), or NULL.  Where the two choices differ, the margin
+ * mu of the comparison that decided them (see tie_margin) is recorded: the
+ * first `max` differences go to pos[] (position in the log) and mu[]; count
+ * counts them all.  Where |mu| < tol the oracle takes the other choice for the
+ * flux (its own log keeps its own choice).
+ */
+typedef struct {
+    const uint8_t *follow;
+    double tol;
+    int64_t *pos;
+    double *mu;
+    int64_t max;
+    int64_t count;
+} orc_ties;
 
 /* ------------------------------------------------------------------------ */
 /* Scalar ENO-MR reconstruction at one face (Sec. 3.2)                       */
@@ -134,135 +255,203 @@ void orc_table_free(orc_table *t) { free(t); }
  * Dot product of a stencil's coefficients with the values of its cells,
  * summed in ascending physical cell order.  coef[l+m] belongs to offset l.
  */
-static double stencil_dot(const double *coef, int m, int n, const double *f, long c, int s)
+static real stencil_dot(const real *coef, int m, int n, const real *f, long c, int s)
 {
     /* cells covered: offsets -m..n; ascending cell order means offsets
        ascending for s = +1 and descending for s = -1. */
-    int l0 = (s > 0) ? -m : n;
-    int dl = (s > 0) ? 1 : -1;
-    int cnt = m + n + 1;
-    int l = l0;
-    double acc = coef[l + m] * FR(l);
-    for (int k = 1; k < cnt; ++k) {
+    int l = (s > 0) ? -m : n;
+    const int dl = (s > 0) ? 1 : -1;
+    real acc = coef[l + m] * FR(l);
+    for (int k = 1; k < m + n + 1; ++k) {
         l += dl;
-        acc = fma(coef[l + m], FR(l), acc);
+        acc = R_FMA(coef[l + m], FR(l), acc);
     }
     return acc;
 }
 
-/*
- * The d-th undivided difference of f at cells first .. first+d (ascending):
- * d rounds of replacing neighbours by f_{i+1} - f_i.  Eq. (CurrentIS) defines
- * IS as h^{m+n} times the (m+n)-th derivative of the stencil's polynomial,
- * which is this difference; the b_l of Table ISCoe are its binomial expansion.
- */
-static double undivided_difference(const double *f, long first, int d)
+/* The value candidate k gives at the face (a stencil's a_l sum, or one of the
+   three minmod branches of Step 3.2, which are the last three candidates). */
+__attribute__((unused)) static real candidate_value(const orc_table *T, const real *f, long c, int s, int k)
 {
-    double t[ORC_MAXW];
-    for (int i = 0; i <= d; ++i) t[i] = f[first + i];
-    for (int lev = 1; lev <= d; ++lev)
-        for (int i = 0; i + lev <= d; ++i) t[i] = t[i + 1] - t[i];
-    return t[0];
+    const int nfull = T->ncand - 3;
+    if (k < nfull) return stencil_dot(T->a[k], T->m[k], T->n[k], f, c, s);
+    const real f0 = FR(0);
+    if (T->m[k] == 0 && T->n[k] == 1) return f0 + (real)0.5 * (FR(1) - f0);   /* S_j^{j+1} */
+    if (T->m[k] == 1 && T->n[k] == 0) return f0 + (real)0.5 * (f0 - FR(-1));  /* S_{j-1}^j */
+    return f0 + (real)0.5 * (real)0;                                         /* S_j^j */
+}
+
+#ifndef ORC_QUAD
+/*
+ * Where the magnitude A_l that rounding acts on comes from (see tie_margin):
+ * |f_l| (row NULL), or sum_i |row_i| |G_i| over the cell's conserved
+ * components (nv values at G + l * nv), or, with per-field alphas,
+ * (sum_i |row_i| |F_i| + ak sum_i |row_i| |U_i|) / 2.
+ */
+typedef struct {
+    const double *row;
+    const double *G;      /* split fluxes [cell][nv] (or U with per-field alphas) */
+    const double *F;      /* per-field alphas: fluxes, stride fstride per cell */
+    long fstride;
+    double ak;
+    int nv;
+} mag_src;
+
+static double mag_at(const mag_src *ms, const double *f, long i)
+{
+    if (!ms || !ms->row) return fabs(f[i]);
+    double a = 0.0;
+    for (int k = 0; k < ms->nv; ++k) a += fabs(ms->row[k]) * fabs(ms->G[i * ms->nv + k]);
+    if (ms->F) {
+        double b = 0.0;
+        for (int k = 0; k < ms->nv; ++k) b += fabs(ms->row[k]) * fabs(ms->F[i * ms->fstride + k]);
+        a = 0.5 * (b + ms->ak * a);
+    }
+    return a;
 }
 
 /*
- * The full stencil (candidate 0) of a characteristic field, evaluated by the
- * caller: is_sum = l_k.(sum b_l G_l) (the indicator before |.|), flux =
- * l_k.(sum a_l G_l), and the operations the field's window projection costs
- * when the reconstruction has to go past candidate 0.
+ * Margin of the comparison that decides between choices `own` and `other` at
+ * one face, on this side's values: d = the earlier of the two in list order.
+ *   - d a stencil with m, n >= 1 (one side accepted it, the other did not):
+ *     mu = (IS_d - IS0) / S, with S the larger of the rounding scales of the
+ *     two sides of the comparison: sum_l |b_l| A_l for IS_d, and
+ *     A_c + 2 A_{c-1} + A_{c-2} (either side of the centre) for IS0.
+ *   - both chose minmod branches (Step 3.2): mu = min(|da|, |db|) / S if one
+ *     took the zero branch (the sign test decided), else (|da| - |db|) / S,
+ *     with da, db the two slopes and S = A_{c+1} + 2 A_c + A_{c-1}.
+ * A_l is the magnitude that rounding acts on when f_l is formed: |f_l| for a
+ * scalar law, sum_i |l_ki| |G_i| for a projected value.  An invalid other
+ * choice gives +infinity.
  */
-typedef struct {
-    double is_sum, flux, fallback_ops;
-} full_stencil;
+#define AR(l) mag_at(ms, f, c + (long)s * (l))
+static double tie_margin(const orc_table *T, const double *f, const mag_src *ms, long c, int s, int own, int other,
+                         const double *is, double is0)
+{
+    if (other < 0 || other >= T->ncand) return INFINITY;
+    const int nfull = T->ncand - 3;
+    const int d = own < other ? own : other;
+    if (d < nfull) {
+        const int m = T->m[d], n = T->n[d];
+        double S = 0.0;
+        for (int l = -m; l <= n; ++l) S += fabs(T->b[d][l + m]) * AR(l);
+        const double s0l = AR(0) + 2.0 * AR(-1) + AR(-2);
+        const double s0r = AR(0) + 2.0 * AR(1) + AR(2);
+        S = fmax(S, fmax(s0l, s0r));
+        return S > 0.0 ? (is[d] - is0) / S : 0.0;
+    }
+    const double da = FR(1) - FR(0), db = FR(0) - FR(-1);
+    const double S = AR(1) + 2.0 * AR(0) + AR(-1);
+    if (!(S > 0.0)) return 0.0;
+    if (own == T->ncand - 1 || other == T->ncand - 1) return fmin(fabs(da), fabs(db)) / S;
+    return (fabs(da) - fabs(db)) / S;
+}
+#undef AR
+
+static void tie_record(orc_ties *t, int64_t pos, double mu)
+{
+    int64_t slot;
+#pragma omp atomic capture
+    slot = t->count++;
+    if (slot < t->max) {
+        if (t->pos) t->pos[slot] = pos;
+        if (t->mu) t->mu[slot] = mu;
+    }
+}
+#endif
 
 /*
- * Reconstruct f-hat at face j+1/2 from cell values f (indexable from
- * j-r+1 to j+r).  sign = +1: f^+ (upwind on the left); sign = -1: f^-.
- * Writes the chosen candidate's position in the candidate list to *idx.
- * pre (optional): candidate 0's indicator and flux, already evaluated.
+ * Reconstruct f-hat at face j+1/2 from cell values f (indexable from j-r+1 to
+ * j+r).  sign = +1: f^+ (upwind on the left); sign = -1: f^-.  Writes the
+ * chosen candidate's position in the candidate list to *idx.  ms (nullable):
+ * where the near-tie margin takes the rounding magnitudes of f; ties
+ * (nullable) with the log position pos of this (face, sign).
  */
-static double recon_face(const orc_table *T, const double *f, long j, int sign, int *idx,
-                         const full_stencil *pre)
+static real recon_face(const orc_table *T, const real *f, const void *msv, long j, int sign, int *idx,
+                       void *tiesv, int64_t pos)
 {
     const int s = sign > 0 ? 1 : -1;
     const long c = sign > 0 ? j : j + 1;
+    const int nfull = T->ncand - 3;   /* candidates 0 .. nfull-1 have m, n >= 1 */
+#ifndef ORC_QUAD
+    orc_ties *ties = (orc_ties *)tiesv;
+    const mag_src *ms = (const mag_src *)msv;
+#else
+    (void)msv; (void)tiesv; (void)pos;
+#endif
 
     /* Step 1: baseline indicator IS0 = min(IS_L, IS_R), Eq. (Baseline_IS). */
-    double f0 = FR(0), fm1 = FR(-1), fm2 = FR(-2), fp1 = FR(1), fp2 = FR(2);
-    double isl = fmax(fabs(f0 - fm1), fabs((f0 - 2.0 * fm1) + fm2));
-    double isr = fmax(fabs(f0 - fp1), fabs((f0 - 2.0 * fp1) + fp2));
-    double is0 = fmin(isl, isr);
+    const real f0 = FR(0), fm1 = FR(-1), fm2 = FR(-2), fp1 = FR(1), fp2 = FR(2);
+    const real isl = R_MAX(R_ABS(f0 - fm1), R_ABS((f0 - (real)2 * fm1) + fm2));
+    const real isr = R_MAX(R_ABS(f0 - fp1), R_ABS((f0 - (real)2 * fp1) + fp2));
+    const real is0 = R_MIN(isl, isr);
     OPS(11);   /* two sides of (sub, mul, sub, add, max), then min */
 
-    /* Step 2: IS of every candidate, Eqs. (CurrentIS), (ISCoe): for the full
-       stencil |sum b_l f_{j+l}|, for the others the undivided difference over
-       the stencil's cells (leftmost physical cell c-m for f^+, c-n for f^-).
-       (The paper only needs them up to the first accepted one; computing all of
-       them and then scanning gives the same choice.) */
-    double is[ORC_MAXC];
-    for (int k = 0; k < T->ncand; ++k) {
-        const int m = T->m[k], n = T->n[k];
-        if (m >= 1 && n >= 1)
-            is[k] = k == 0 ? fabs(pre ? pre->is_sum : stencil_dot(T->b[k], m, n, f, c, s))
-                           : fabs(undivided_difference(f, s > 0 ? c - m : c - n, m + n));
-        else
-            is[k] = 0.0;
-    }
-
-    /* Step 3.1: first candidate in list order with m, n >= 1 and IS < IS0. */
-    double scan = 0.0;     /* ops of the b_l chains of candidates 1.. scanned so far */
-    int tested = 0;        /* candidates 1.. tested so far */
-    const int r = T->r;
-    const double table = (double)((2 * r - 2) * (2 * r - 1) / 2 - 1);
-    for (int k = 0; k < T->ncand; ++k) {
-        if (T->m[k] >= 1 && T->n[k] >= 1) {
-            const int d = T->m[k] + T->n[k];
-            if (k == 0) OPS(pre ? 1 : 2 * d + 1 + 1);     /* (b_l chain and) compare */
-            else { scan += 2 * d + 1 + 1; ++tested; }
-            if (is[k] < is0) {
-                if (k > 0) OPS(scan < table + tested ? scan : table + tested);
-                *idx = k;
-                if (k == 0 && pre) return pre->flux;
-                OPS(2 * d + 1);                 /* a_l chain */
-                return stencil_dot(T->a[k], T->m[k], T->n[k], f, c, s);
-            }
-            /* past candidate 0: the field's window must be projected */
-            if (k == 0 && pre) OPS(pre->fallback_ops);
+    /* Steps 2 and 3.1: the indicators of the candidates with m, n >= 1 in list
+       order, Eqs. (CurrentIS), (ISCoe); the first with IS < IS0 is taken.
+       (A near-tie margin needs the indicator of a candidate at or before the
+       accepted one, so the early exit leaves every one it can need.) */
+    real is[ORC_MAXC];
+    int own = -1;
+    for (int k = 0; k < nfull; ++k) {
+        is[k] = R_ABS(stencil_dot(T->b[k], T->m[k], T->n[k], f, c, s));
+        OPS(T->m[k] + T->n[k] + 1 + 1);   /* b_l chain and the compare */
+        if (is[k] < is0) {
+            own = k;
+            break;
         }
     }
-    OPS(scan < table + tested ? scan : table + tested);
-    OPS(7);   /* minmod: two slopes, their product, compare, |.| compare, f0 + mm/2 */
-
-    /* Step 3.2: minmod between S_j^{j+1} and S_{j-1}^j, else S_j^j. */
-    double da = fp1 - f0;      /* slope towards the downwind neighbour */
-    double db = f0 - fm1;      /* slope towards the upwind neighbour   */
-    double mm;
-    int pick_m, pick_n;
-    if (da * db > 0.0) {
-        if (fabs(da) <= fabs(db)) { mm = da; pick_m = 0; pick_n = 1; }
-        else { mm = db; pick_m = 1; pick_n = 0; }
+    real out;
+    if (own >= 0) {
+        OPS(T->m[own] + T->n[own] + 1);       /* the a_l chain */
+        out = stencil_dot(T->a[own], T->m[own], T->n[own], f, c, s);
     } else {
-        mm = 0.0; pick_m = 0; pick_n = 0;
+        /* Step 3.2: minmod between S_j^{j+1} and S_{j-1}^j, else S_j^j. */
+        OPS(7);   /* two slopes, their product, compare, |.| compare, f0 + mm/2 */
+        const real da = fp1 - f0;      /* slope towards the downwind neighbour */
+        const real db = f0 - fm1;      /* slope towards the upwind neighbour   */
+        real mm;
+        int pm, pn;
+        if (da * db > (real)0) {
+            if (R_ABS(da) <= R_ABS(db)) { mm = da; pm = 0; pn = 1; }
+            else { mm = db; pm = 1; pn = 0; }
+        } else {
+            mm = (real)0; pm = 0; pn = 0;
+        }
+        own = T->ncand - 1;
+        for (int k = nfull; k < T->ncand; ++k)
+            if (T->m[k] == pm && T->n[k] == pn) own = k;
+        out = f0 + (real)0.5 * mm;
     }
-    *idx = T->ncand - 1;
-    for (int k = 0; k < T->ncand; ++k)
-        if (T->m[k] == pick_m && T->n[k] == pick_n) *idx = k;
-    return f0 + 0.5 * mm;
+    *idx = own;
+#ifndef ORC_QUAD
+    if (ties && ties->follow) {
+        const int other = ties->follow[pos];
+        if (other != own) {
+            const double mu = tie_margin(T, f, ms, c, s, own, other, is, is0);
+            tie_record(ties, pos, mu);
+            if (fabs(mu) < ties->tol) out = candidate_value(T, f, c, s, other);
+        }
+    }
+#endif
+    return out;
 }
 #undef FR
 
 /*
  * Bare scalar reconstruction over n faces.  f_with_halo has n + 2r - 1
- * entries; face i lies between array cells i + r - 1 and i + r.
+ * entries; face i lies between array cells i + r - 1 and i + r.  Log
+ * position of face i: i.
  */
-int orc_recon_faces(const orc_table *T, int sign, long n, const double *f_with_halo,
-                    double *fhat, uint8_t *idx)
+int ORC_FN(orc_recon_faces)(const orc_table *T, int sign, long n, const real *f_with_halo, real *fhat,
+                            uint8_t *idx, void *ties)
 {
     if (!T || n < 0 || (sign != 1 && sign != -1)) return ORC_EINVAL;
     const int r = T->r;
+    ops_off();   /* the operation count covers the Euler operator */
     for (long i = 0; i < n; ++i) {
         int k;
-        fhat[i] = recon_face(T, f_with_halo, i + r - 1, sign, &k, NULL);
+        fhat[i] = recon_face(T, f_with_halo, NULL, i + r - 1, sign, &k, ties, i);
         if (idx) idx[i] = (uint8_t)k;
     }
     return ORC_OK;
@@ -288,9 +477,9 @@ static long map_cell(long i, long n, int bc)
 /* Scalar conservation law on one line                                       */
 /* ------------------------------------------------------------------------ */
 
-static double scalar_flux(int flux, double a, double u)
+static real scalar_flux(int flux, real a, real u)
 {
-    return flux == ORC_ADVECTION ? a * u : 0.5 * u * u;
+    return flux == ORC_ADVECTION ? a * u : (real)0.5 * u * u;
 }
 
 /*
@@ -298,53 +487,204 @@ static double scalar_flux(int flux, double a, double u)
  * then f-hat = f-hat^+ + f-hat^- at faces f = 0..n (face f between cells f-1
  * and f), and du/dt = -(f-hat_{j+1/2} - f-hat_{j-1/2}) / h (Eq. 1DWENOFD).
  * With split == NONE the flux itself is reconstructed as f^+ (Sec. 4.2).
- * idx (optional): 2 entries per face, [+, -].
+ * idx (optional): 2 entries per face, [+, -] (log positions 2f, 2f+1).
  */
-int orc_scalar_rhs(const orc_table *T, int flux, double a, int split, int bc, long n,
-                   double ih, const double *u, double *dudt, uint8_t *idx, double *alpha_out)
+int ORC_FN(orc_scalar_rhs)(const orc_table *T, int flux, real a, int split, int bc, long n, real ih,
+                           const real *u, real *dudt, uint8_t *idx, real *alpha_out, void *ties)
 {
     if (!T || n < 2) return ORC_EINVAL;
     const long g = T->r + 1;
     const long nn = n + 2 * g;
-    double *fp = (double *)malloc(sizeof(double) * nn);
-    double *fm = (double *)malloc(sizeof(double) * nn);
-    double *fh = (double *)malloc(sizeof(double) * (n + 1));
+    real *fp = (real *)malloc(sizeof(real) * nn);
+    real *fm = (real *)malloc(sizeof(real) * nn);
+    real *fh = (real *)malloc(sizeof(real) * (n + 1));
     if (!fp || !fm || !fh) { free(fp); free(fm); free(fh); return ORC_EINVAL; }
 
-    double alpha = 0.0;
+    real alpha = 0;
     for (long i = 0; i < n; ++i) {
-        double d = flux == ORC_ADVECTION ? fabs(a) : fabs(u[i]);
+        real d = flux == ORC_ADVECTION ? R_ABS(a) : R_ABS(u[i]);
         if (d > alpha) alpha = d;
     }
     if (alpha_out) *alpha_out = alpha;
 
     for (long i = 0; i < nn; ++i) {
-        double ui = u[map_cell(i - g, n, bc)];
-        double fi = scalar_flux(flux, a, ui);
+        real ui = u[map_cell(i - g, n, bc)];
+        real fi = scalar_flux(flux, a, ui);
         if (split == ORC_SPLIT_LF) {
-            double t = alpha * ui;
-            fp[i] = 0.5 * (fi + t);
-            fm[i] = 0.5 * (fi - t);
+            real t = alpha * ui;
+            fp[i] = (real)0.5 * (fi + t);
+            fm[i] = (real)0.5 * (fi - t);
         } else {
             fp[i] = fi;
-            fm[i] = 0.0;
+            fm[i] = 0;
         }
     }
+#pragma omp parallel if (n >= 4096)
+    {
+    ops_off();   /* the operation count covers the Euler operator */
+#pragma omp for schedule(static)
     for (long f = 0; f <= n; ++f) {
         long j = f - 1 + g;           /* left cell of face f in the ghosted array */
-        int kp, km;
-        double hp = recon_face(T, fp, j, +1, &kp, NULL);
-        double hm = 0.0;
-        km = 0;
-        if (split == ORC_SPLIT_LF) hm = recon_face(T, fm, j, -1, &km, NULL);
+        int kp, km = 0;
+        real hp = recon_face(T, fp, NULL, j, +1, &kp, ties, 2 * (int64_t)f);
+        real hm = 0;
+        if (split == ORC_SPLIT_LF) hm = recon_face(T, fm, NULL, j, -1, &km, ties, 2 * (int64_t)f + 1);
         fh[f] = hp + hm;
         if (idx) { idx[2 * f] = (uint8_t)kp; idx[2 * f + 1] = (uint8_t)km; }
+    }
     }
     for (long i = 0; i < n; ++i) dudt[i] = -((fh[i + 1] - fh[i]) * ih);
     free(fp); free(fm); free(fh);
     return ORC_OK;
 }
 
+/*
+ * Linear SSP-RK(m, m-1) step for a scalar line (Eq. lSSPRK):
+ * u^(s) = u^(s-1) + dt/2 L(u^(s-1)), s = 1..m-1, and
+ * u^{n+1} = sum_{k<m-1} a_k u^(k) + a_{m-1} (u^(m-1) + dt/2 L(u^(m-1))).
+ * coef holds a_0..a_{m-1} (exact fractions from the caller, Eq. lSSPRK_Coe,
+ * each rounded by one division).
+ */
+static int lssp_run(const orc_table *T, int flux, real a, int split, int bc, long n, real ih, real dt, long nsteps,
+                    int m, const real *coef, real *u)
+{
+    if (m < 2 || m > 32) return ORC_EINVAL;
+    real *stages = (real *)malloc(sizeof(real) * n * m);
+    real *L = (real *)malloc(sizeof(real) * n);
+    real *acc = (real *)malloc(sizeof(real) * n);
+    int st = ORC_OK;
+    if (!stages || !L || !acc) { st = ORC_EINVAL; goto done; }
+    const real hdt = (real)0.5 * dt;
+    for (long step = 0; step < nsteps; ++step) {
+        memcpy(stages, u, sizeof(real) * n);
+        for (int s = 1; s < m; ++s) {
+            if ((st = ORC_FN(orc_scalar_rhs)(T, flux, a, split, bc, n, ih, stages + (s - 1) * n, L, NULL, NULL,
+                                             NULL)))
+                goto done;
+            for (long i = 0; i < n; ++i) stages[s * n + i] = stages[(s - 1) * n + i] + hdt * L[i];
+        }
+        if ((st = ORC_FN(orc_scalar_rhs)(T, flux, a, split, bc, n, ih, stages + (m - 1) * n, L, NULL, NULL, NULL)))
+            goto done;
+        for (long i = 0; i < n; ++i) acc[i] = 0;
+        for (int k = 0; k < m - 1; ++k)
+            for (long i = 0; i < n; ++i) acc[i] = acc[i] + coef[k] * stages[k * n + i];
+        for (long i = 0; i < n; ++i)
+            u[i] = acc[i] + coef[m - 1] * (stages[(m - 1) * n + i] + hdt * L[i]);
+    }
+done:
+    free(stages); free(L); free(acc);
+    return st;
+}
+
+static int lssp_coefs(int m, const int64_t *cnum, const int64_t *cden, real *coef)
+{
+    if (m < 2 || m > 32) return ORC_EINVAL;
+    for (int k = 0; k < m; ++k) coef[k] = (real)cnum[k] / (real)cden[k];
+    return ORC_OK;
+}
+
+int ORC_FN(orc_scalar_lssp_run)(const orc_table *T, int flux, real a, int split, int bc, long n, real ih, real dt,
+                                long nsteps, int m, const int64_t *cnum, const int64_t *cden, real *u)
+{
+    real coef[32];
+    if (lssp_coefs(m, cnum, cden, coef)) return ORC_EINVAL;
+    return lssp_run(T, flux, a, split, bc, n, ih, dt, nsteps, m, coef, u);
+}
+
+/*
+ * SSP-RK3 stage combination (Eq. TVD3rdRK), elementwise over n values:
+ *   stage 1: out = us + dt L
+ *   stage 2: out = 3/4 un + 1/4 (us + dt L)
+ *   stage 3: out = 1/3 un + 2/3 (us + dt L)
+ */
+void ORC_FN(orc_ssprk3_combine)(int stage, long n, const real *un, const real *us, const real *L, real dt,
+                                real *out)
+{
+    const real c13 = (real)1 / (real)3, c23 = (real)2 / (real)3;
+    ops_enter(ORC_OPS_RK);
+    OPS((stage == 1 ? 2 : 5) * n);
+    ops_flush();
+    for (long i = 0; i < n; ++i) {
+        real e = us[i] + dt * L[i];
+        if (stage == 1) out[i] = e;
+        else if (stage == 2) out[i] = (real)0.75 * un[i] + (real)0.25 * e;
+        else out[i] = c13 * un[i] + c23 * e;
+    }
+}
+
+/*
+ * SSP-RK3 run of a scalar line with a fixed step dt; the last step is cut so
+ * that the run ends exactly at t_end (if t_end > 0, else nsteps steps).
+ */
+int ORC_FN(orc_scalar_ssprk3_run)(const orc_table *T, int flux, real a, int split, int bc, long n, real ih, real dt,
+                                  real t_end, long nsteps, real *u)
+{
+    real *un = (real *)malloc(sizeof(real) * n);
+    real *us = (real *)malloc(sizeof(real) * n);
+    real *L = (real *)malloc(sizeof(real) * n);
+    int st = ORC_OK;
+    if (!un || !us || !L) { st = ORC_EINVAL; goto done; }
+    real t = 0;
+    for (long step = 0; t_end > 0 ? t < t_end : step < nsteps; ++step) {
+        real h = dt;
+        if (t_end > 0 && t + h > t_end) h = t_end - t;
+        memcpy(un, u, sizeof(real) * n);
+        memcpy(us, u, sizeof(real) * n);
+        for (int s = 1; s <= 3; ++s) {
+            if ((st = ORC_FN(orc_scalar_rhs)(T, flux, a, split, bc, n, ih, us, L, NULL, NULL, NULL))) goto done;
+            ORC_FN(orc_ssprk3_combine)(s, n, un, us, L, h, us);
+        }
+        memcpy(u, us, sizeof(real) * n);
+        t = t + h;
+    }
+done:
+    free(un); free(us); free(L);
+    return st;
+}
+
+#ifdef ORC_QUAD
+/*
+ * The linear convergence test of Sec. 4.1 in binary128, start to finish:
+ * u0 = lam sin^alpha(pi x) on the n nodes x_j = -1 + (j-1) h, h = 2/n,
+ * periodic, linear advection with a = 1, LF split, linear SSP-RK(m, m-1) with
+ * dt = h to t = 2 (n steps), after which the exact solution is u0 again.
+ * Errors: L1 = mean of |u - u0| over the n+1 points x_1 .. x_{n+1} (the
+ * periodic end point counted twice), Linf = max; both rounded to double.
+ */
+int orc_q_advection_errors(const orc_table *T, int alpha, double lam, long n, int m, const int64_t *cnum,
+                           const int64_t *cden, double *l1, double *linf)
+{
+    if (!T || n < 2 * T->r + 1) return ORC_EINVAL;
+    real *u0 = (real *)malloc(sizeof(real) * n);
+    real *u = (real *)malloc(sizeof(real) * n);
+    if (!u0 || !u) { free(u0); free(u); return ORC_EINVAL; }
+    const real h = (real)2 / (real)n;
+    for (long j = 0; j < n; ++j) {
+        const real x = (real)-1 + (real)j * h;
+        real sv = sinq(M_PIq * x), p = 1;
+        for (int k = 0; k < alpha; ++k) p = p * sv;
+        u0[j] = (real)lam * p;
+        u[j] = u0[j];
+    }
+    int st = ORC_FN(orc_scalar_lssp_run)(T, ORC_ADVECTION, (real)1, ORC_SPLIT_LF, ORC_PERIODIC, n, (real)1 / h, h, n,
+                                         m, cnum, cden, u);
+    if (!st) {
+        real s = 0, mx = 0;
+        for (long j = 0; j < n; ++j) {
+            const real e = fabsq(u[j] - u0[j]);
+            s = s + e;
+            if (e > mx) mx = e;
+        }
+        s = s + fabsq(u[0] - u0[0]);
+        *l1 = (double)(s / (real)(n + 1));
+        *linf = (double)mx;
+    }
+    free(u0); free(u);
+    return st;
+}
+#endif
+
+#ifndef ORC_QUAD
 /* ------------------------------------------------------------------------ */
 /* Euler equations: one line in the face-normal frame                        */
 /* ------------------------------------------------------------------------ */
@@ -354,24 +694,25 @@ int orc_scalar_rhs(const orc_table *T, int flux, double a, int split, int bc, lo
  * conserved variables, the momentum m_n normal to the faces.
  */
 typedef struct {
-    double un, ut, p, c, H;
+    double un, ut, p, c, H, sq;
     double F[4];
 } cell_prim;
 
+/* Primitive quantities and fluxes of one cell (18 ops for nv = 4, 14 for nv = 3). */
 static int primitives(int nv, double gamma, const double *U, cell_prim *q)
 {
-    double rho = U[0], mn = U[1], mt = nv == 4 ? U[2] : 0.0, E = U[nv - 1];
-    double ir = 1.0 / rho;
-    double un = mn * ir;
-    double ut = nv == 4 ? mt * ir : 0.0;
-    double ke = nv == 4 ? 0.5 * (mn * un + mt * ut) : 0.5 * (mn * un);
-    double p = (gamma - 1.0) * (E - ke);
+    const double rho = U[0], mn = U[1], mt = nv == 4 ? U[2] : 0.0, E = U[nv - 1];
+    const double un = mn / rho;
+    const double ut = nv == 4 ? mt / rho : 0.0;
+    const double ke = nv == 4 ? 0.5 * (mn * un + mt * ut) : 0.5 * (mn * un);
+    const double p = (gamma - 1.0) * (E - ke);
     if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(mn)) return ORC_ENONPHYS;
     q->un = un;
     q->ut = ut;
     q->p = p;
-    q->c = sqrt((gamma * p) * ir);
-    q->H = (E + p) * ir;
+    q->c = sqrt(gamma * p / rho);
+    q->H = (E + p) / rho;
+    q->sq = sqrt(rho);                 /* the cell's Roe weight */
     q->F[0] = mn;
     q->F[1] = mn * un + p;
     if (nv == 4) {
@@ -384,60 +725,70 @@ static int primitives(int nv, double gamma, const double *U, cell_prim *q)
 }
 
 /*
- * Roe-averaged eigenvectors at the face between states UL and UR
- * (Sec. 4 preamble).  Fields are ordered (u-c, u, [shear,] u+c); Lm is the
- * inverse of Rm.  Returns nonzero if the averaged sound speed is not real.
+ * Roe-averaged eigenvectors at the face between cells with primitives qL, qR
+ * (Sec. 4 preamble): the Roe state from sqrt(rho) weights, c^2 = (gamma-1)
+ * (H - q^2/2), and the closed-form right eigenvectors of the face-normal flux
+ * Jacobian for the fields (u-c, u, [shear,] u+c), with Lm = Rm^{-1} written
+ * with k = (gamma-1)/c^2.  Returns nonzero if c^2 is not positive.
+ * 42 ops for nv = 4, 34 for nv = 3.
  */
-static int roe_eigen(int nv, double gamma, const double *UL, const cell_prim *qL,
-                     const double *UR, const cell_prim *qR, double Lm[4][4], double Rm[4][4])
+static int roe_eigen(int nv, double gamma, const cell_prim *qL, const cell_prim *qR, double Lm[4][4],
+                     double Rm[4][4])
 {
-    double sL = sqrt(UL[0]);
-    double sR = sqrt(UR[0]);
-    double id = 1.0 / (sL + sR);
-    double u = (sL * qL->un + sR * qR->un) * id;
-    double v = nv == 4 ? (sL * qL->ut + sR * qR->ut) * id : 0.0;
-    double H = (sL * qL->H + sR * qR->H) * id;
-    double q2 = nv == 4 ? u * u + v * v : u * u;
-    double c2 = (gamma - 1.0) * (H - 0.5 * q2);
+    const double sL = qL->sq, sR = qR->sq;
+    const double den = sL + sR;
+    const double u = (sL * qL->un + sR * qR->un) / den;
+    const double v = nv == 4 ? (sL * qL->ut + sR * qR->ut) / den : 0.0;
+    const double H = (sL * qL->H + sR * qR->H) / den;
+    const double q2 = nv == 4 ? u * u + v * v : u * u;
+    const double hq2 = 0.5 * q2;
+    const double c2 = (gamma - 1.0) * (H - hq2);
     if (!(c2 > 0.0)) return ORC_ENONPHYS;
-    double c = sqrt(c2);
-    double k = (gamma - 1.0) / c2;
-    double ic = 1.0 / c;
-    double hq = 0.5 * k * q2;
-    double ku = k * u;
-    double uic = u * ic;
-    double uc = u * c;
+    const double c = sqrt(c2);
+    const double k = (gamma - 1.0) / c2;
+    const double hk = 0.5 * k;
+    const double hq = hk * q2;
+    const double uic = u / c;
+    const double ic = 1.0 / c;
+    const double ku = k * u;
+    const double uc = u * c;
+    memset(Lm, 0, sizeof(double) * 16);
+    memset(Rm, 0, sizeof(double) * 16);
     if (nv == 4) {
-        double kv = k * v;
-        double L[4][4] = {
-            {0.5 * (hq + uic), -0.5 * (ku + ic), -0.5 * kv, 0.5 * k},
+        const double kv = k * v;
+        const double lv = -0.5 * kv;
+        const double L[4][4] = {
+            {0.5 * (hq + uic), -0.5 * (ku + ic), lv, hk},
             {1.0 - hq, ku, kv, -k},
             {-v, 0.0, 1.0, 0.0},
-            {0.5 * (hq - uic), -0.5 * (ku - ic), -0.5 * kv, 0.5 * k},
+            {0.5 * (hq - uic), -0.5 * (ku - ic), lv, hk},
         };
-        double R[4][4] = {
+        const double R[4][4] = {
             {1.0, 1.0, 0.0, 1.0},
             {u - c, u, 0.0, u + c},
             {v, v, 1.0, v},
-            {H - uc, 0.5 * q2, v, H + uc},
+            {H - uc, hq2, v, H + uc},
         };
         memcpy(Lm, L, sizeof(L));
         memcpy(Rm, R, sizeof(R));
+        OPS(42);
     } else {
-        double L[4][4] = {
-            {0.5 * (hq + uic), -0.5 * (ku + ic), 0.5 * k, 0.0},
-            {1.0 - hq, ku, -k, 0.0},
-            {0.5 * (hq - uic), -0.5 * (ku - ic), 0.5 * k, 0.0},
-            {0.0, 0.0, 0.0, 0.0},
+        const double L[3][3] = {
+            {0.5 * (hq + uic), -0.5 * (ku + ic), hk},
+            {1.0 - hq, ku, -k},
+            {0.5 * (hq - uic), -0.5 * (ku - ic), hk},
         };
-        double R[4][4] = {
-            {1.0, 1.0, 1.0, 0.0},
-            {u - c, u, u + c, 0.0},
-            {H - uc, 0.5 * q2, H + uc, 0.0},
-            {0.0, 0.0, 0.0, 0.0},
+        const double R[3][3] = {
+            {1.0, 1.0, 1.0},
+            {u - c, u, u + c},
+            {H - uc, hq2, H + uc},
         };
-        memcpy(Lm, L, sizeof(L));
-        memcpy(Rm, R, sizeof(R));
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                Lm[i][j] = L[i][j];
+                Rm[i][j] = R[i][j];
+            }
+        OPS(34);
     }
     return ORC_OK;
 }
@@ -448,7 +799,7 @@ int orc_roe_eigen(int nv, double gamma, const double *UL, const double *UR, doub
     cell_prim qL, qR;
     if (primitives(nv, gamma, UL, &qL) || primitives(nv, gamma, UR, &qR)) return ORC_ENONPHYS;
     double Lm[4][4], Rm[4][4];
-    int st = roe_eigen(nv, gamma, UL, &qL, UR, &qR, Lm, Rm);
+    int st = roe_eigen(nv, gamma, &qL, &qR, Lm, Rm);
     for (int i = 0; i < nv; ++i)
         for (int j = 0; j < nv; ++j) {
             Lout[i * nv + j] = Lm[i][j];
@@ -457,18 +808,11 @@ int orc_roe_eigen(int nv, double gamma, const double *UL, const double *UR, doub
     return st;
 }
 
+/* sum_i row[i] x[i] as an fma chain over ascending i (nv ops). */
 static double row_dot(const double *row, const double *x, int nv)
 {
     double acc = row[0] * x[0];
     for (int i = 1; i < nv; ++i) acc = fma(row[i], x[i], acc);
-    return acc;
-}
-
-/* A row of L applied to a split flux: the chain from the last component down. */
-static double project_dot(const double *row, const double *x, int nv)
-{
-    double acc = row[nv - 1] * x[nv - 1];
-    for (int i = nv - 2; i >= 0; --i) acc = fma(row[i], x[i], acc);
     return acc;
 }
 
@@ -526,31 +870,29 @@ typedef struct {
     int per_field;
 } euler_var;
 
-static const euler_var k_default_var = {0, 0};
-
 /*
  * Numerical fluxes at faces f = 0..n of one line (face f between cells f-1
  * and f).  Ul is [nv][n] in the face-normal frame.  Fhat is [n+1][nv].
  * alpha: the line's alpha, or its three per-field alphas (var.per_field).
  * idx (optional) holds nv*2 entries per face: [(field)*2 + (0:+, 1:-)].
+ * ties (nullable): the near-tie record; the log position of (face f, field
+ * k, sign index sg) is pos0 + f * fstride + 2k + sg.  par: faces in parallel
+ * (for a line that is alone; the 2D operator parallelises over lines).
  */
-static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, long n,
-                             const double *Ul, const double *alpha, euler_var var, double *Fhat,
-                             uint8_t *idx)
+static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, long n, const double *Ul,
+                             const double *alpha, euler_var var, double *Fhat, uint8_t *idx, orc_ties *ties,
+                             int64_t pos0, int64_t fstride, int par)
 {
     const long g = T->r + 1;
     const long nn = n + 2 * g;
+    const int W = 2 * T->r - 1;
     double *U = (double *)malloc(sizeof(double) * nn * nv);
     double *Gp = (double *)malloc(sizeof(double) * nn * nv);
     double *Gm = (double *)malloc(sizeof(double) * nn * nv);
     cell_prim *Q = (cell_prim *)malloc(sizeof(cell_prim) * nn);
-    double *wp = (double *)malloc(sizeof(double) * nn);
-    double *wm = (double *)malloc(sizeof(double) * nn);
     int st = ORC_OK;
-    const int counting = g_counting;
-    /* the operation counter covers the default operator only */
-    if (var.componentwise || var.per_field) g_counting = 0;
-    if (!U || !Gp || !Gm || !Q || !wp || !wm) { st = ORC_EINVAL; goto done; }
+    const int counting = !var.componentwise && !var.per_field;
+    if (!U || !Gp || !Gm || !Q) { st = ORC_EINVAL; goto done; }
 
     /* Ghosted line, primitive quantities and the LF split G = (F +- alpha U)/2
        (with per-field alphas the split is taken after the projection). */
@@ -563,106 +905,97 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
             Gp[i * nv + v] = 0.5 * (Q[i].F[v] + t);
             Gm[i * nv + v] = 0.5 * (Q[i].F[v] - t);
         }
-        /* once per cell of the line (ghosts are copies): 1/rho, velocities,
-           kinetic energy, p, E + p, H, fluxes, the split (5 per component) and
-           sqrt(rho) of the Roe average */
-        if (i >= g && i < g + n) OPS(nv == 4 ? 36 : 27);
+        /* once per cell of the line: the primitives and fluxes, and the split
+           (t, the sum and the difference, two halvings: 5 per component) */
+        if (counting && i >= g && i < g + n) OPS((nv == 4 ? 18 : 14) + 5 * nv);
     }
 
-    for (long f = 0; f <= n; ++f) {
-        long j = f - 1 + g;      /* left cell of the face in the ghosted line */
-        double Lm[4][4], Rm[4][4];
-        /* a periodic line's face n is its face 0 again: counted once */
-        g_counting = counting && !var.componentwise && !var.per_field && !(bc == ORC_PERIODIC && f == n);
-        if (var.componentwise) {
-            /* G+- of each component reconstructed as they are */
-            for (int k = 0; k < nv; ++k) {
-                for (long i = j - T->r + 1; i <= j + T->r; ++i) {
-                    wp[i] = Gp[i * nv + k];
-                    wm[i] = Gm[i * nv + k];
-                }
-                int kp, km;
-                double hp = recon_face(T, wp, j, +1, &kp, NULL);
-                double hm = recon_face(T, wm, j, -1, &km, NULL);
-                Fhat[f * nv + k] = hp + hm;
-                if (idx) {
-                    idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
-                    idx[(f * nv + k) * 2 + 1] = (uint8_t)km;
-                }
-            }
-            continue;
-        }
-        if ((st = roe_eigen(nv, gamma, &U[j * nv], &Q[j], &U[(j + 1) * nv], &Q[j + 1], Lm, Rm)))
-            goto done;
-        /* Roe average and the entries of L and R used below (0.5 q^2 is shared
-           by c^2 and R) */
-        OPS(nv == 4 ? 44 : 36);
-        const int W = 2 * T->r - 1;
-        const double proj = nv == 4 ? 20 : 14;
-        /* the full stencil of every field by linearity: per sign the a_l and
-           b_l sums of each split-flux component, then their projections */
-        full_stencil pre[4][2];
-        if (!var.per_field) {
-            double A[2][4], B[2][4];
-            for (int sg = 0; sg < 2; ++sg) {
-                const double *G = sg == 0 ? Gp : Gm;
-                const long cc = sg == 0 ? j : j + 1;
-                const int ss = sg == 0 ? 1 : -1;
-                for (int v = 0; v < nv; ++v) {
-                    for (long i = j - T->r + 1; i <= j + T->r; ++i) wp[i] = G[i * nv + v];
-                    A[sg][v] = stencil_dot(T->a[0], T->m[0], T->n[0], wp, cc, ss);
-                    B[sg][v] = stencil_dot(T->b[0], T->m[0], T->n[0], wp, cc, ss);
-                }
-            }
-            for (int k = 0; k < nv; ++k)
-                for (int sg = 0; sg < 2; ++sg) {
-                    pre[k][sg].is_sum = project_dot(Lm[k], B[sg], nv);
-                    pre[k][sg].flux = project_dot(Lm[k], A[sg], nv);
-                    /* one row of L over the window cells beyond the five
-                       centre cells IS0 uses: u-c, u+c and u rows 3 fma and a
-                       product (2 fma and a product in 1D), the shear row one fma */
-                    pre[k][sg].fallback_ops = (W - 5) * (nv == 4 ? (k == 2 ? 2 : 7) : 5);
-                }
-            /* per sign: L G at the five centre cells, 2 nv chains of W terms,
-               and the projection of the a_l and b_l sums */
-            OPS(2 * (5 * proj + 2 * nv * (2 * W - 1) + 2 * proj));
+    const int cat = t_cat;
+#pragma omp parallel if (par)
+    {
+        ops_enter(cat);
+        if (!counting) t_count = 0;
+        double *wp = (double *)malloc(sizeof(double) * nn);
+        double *wm = (double *)malloc(sizeof(double) * nn);
+        if (!wp || !wm) {
+#pragma omp atomic write
+            st = ORC_EINVAL;
         } else {
-            /* L F and L U over each window (2r-1 cells per sign) */
-            OPS(2 * W * proj);
-        }
-        double what[4];
-        for (int k = 0; k < nv; ++k) {
-            /* characteristic field k of the split fluxes over the face's window */
-            if (var.per_field) {
-                const double ak = alpha[field_speed(nv, k)];
-                for (long i = j - T->r + 1; i <= j + T->r; ++i) {
-                    double pf = project_dot(Lm[k], Q[i].F, nv);
-                    double t = ak * project_dot(Lm[k], &U[i * nv], nv);
-                    wp[i] = 0.5 * (pf + t);
-                    wm[i] = 0.5 * (pf - t);
+#pragma omp for schedule(static)
+            for (long f = 0; f <= n; ++f) {
+                const long j = f - 1 + g;      /* left cell of the face in the ghosted line */
+                /* a periodic line's face n is its face 0 again: counted once */
+                t_count = counting && g_count_on && !(bc == ORC_PERIODIC && f == n);
+                if (var.componentwise) {
+                    for (int k = 0; k < nv; ++k) {
+                        for (long i = j - T->r + 1; i <= j + T->r; ++i) {
+                            wp[i] = Gp[i * nv + k];
+                            wm[i] = Gm[i * nv + k];
+                        }
+                        int kp, km;
+                        const int64_t pk = pos0 + f * fstride + 2 * k;
+                        double hp = recon_face(T, wp, NULL, j, +1, &kp, ties, pk);
+                        double hm = recon_face(T, wm, NULL, j, -1, &km, ties, pk + 1);
+                        Fhat[f * nv + k] = hp + hm;
+                        if (idx) {
+                            idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
+                            idx[(f * nv + k) * 2 + 1] = (uint8_t)km;
+                        }
+                    }
+                    continue;
                 }
-            } else {
-                for (long i = j - T->r + 1; i <= j + T->r; ++i) {
-                    wp[i] = project_dot(Lm[k], &Gp[i * nv], nv);
-                    wm[i] = project_dot(Lm[k], &Gm[i * nv], nv);
+                double Lm[4][4], Rm[4][4];
+                if (roe_eigen(nv, gamma, &Q[j], &Q[j + 1], Lm, Rm)) {
+#pragma omp atomic write
+                    st = ORC_ENONPHYS;
+                    continue;
                 }
-            }
-            int kp, km;
-            double hp = recon_face(T, wp, j, +1, &kp, var.per_field ? NULL : &pre[k][0]);
-            double hm = recon_face(T, wm, j, -1, &km, var.per_field ? NULL : &pre[k][1]);
-            what[k] = hp + hm;
-            if (idx) {
-                idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
-                idx[(f * nv + k) * 2 + 1] = (uint8_t)km;
+                /* the projection of every window cell onto every field: per
+                   sign W cells, nv rows of nv terms */
+                OPS(2 * W * nv * nv);
+                double what[4];
+                for (int k = 0; k < nv; ++k) {
+                    /* characteristic field k of the split fluxes over the face's window */
+                    mag_src msp = {Lm[k], Gp, NULL, 0, 0.0, nv}, msm = {Lm[k], Gm, NULL, 0, 0.0, nv};
+                    if (var.per_field) {
+                        const double ak = alpha[field_speed(nv, k)];
+                        for (long i = j - T->r + 1; i <= j + T->r; ++i) {
+                            const double pf = row_dot(Lm[k], Q[i].F, nv);
+                            const double t = ak * row_dot(Lm[k], &U[i * nv], nv);
+                            wp[i] = 0.5 * (pf + t);
+                            wm[i] = 0.5 * (pf - t);
+                        }
+                        msp.G = msm.G = U;
+                        msp.F = msm.F = Q[0].F;
+                        msp.fstride = msm.fstride = (long)(sizeof(cell_prim) / sizeof(double));
+                        msp.ak = msm.ak = ak;
+                    } else {
+                        for (long i = j - T->r + 1; i <= j + T->r; ++i) {
+                            wp[i] = row_dot(Lm[k], &Gp[i * nv], nv);
+                            wm[i] = row_dot(Lm[k], &Gm[i * nv], nv);
+                        }
+                    }
+                    int kp, km;
+                    const int64_t pk = pos0 + f * fstride + 2 * k;
+                    double hp = recon_face(T, wp, &msp, j, +1, &kp, ties, pk);
+                    double hm = recon_face(T, wm, &msm, j, -1, &km, ties, pk + 1);
+                    what[k] = hp + hm;
+                    if (idx) {
+                        idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
+                        idx[(f * nv + k) * 2 + 1] = (uint8_t)km;
+                    }
+                }
+                /* back to conserved components: w-hat+ + w-hat-, then F-hat = R w-hat */
+                for (int v = 0; v < nv; ++v) Fhat[f * nv + v] = row_dot(Rm[v], what, nv);
+                OPS(nv + nv * nv);
             }
         }
-        /* back to conserved components: F-hat = R w-hat (w-hat+ + w-hat- first) */
-        for (int v = 0; v < nv; ++v) Fhat[f * nv + v] = row_dot(Rm[v], what, nv);
-        OPS(nv == 4 ? 4 + 20 : 3 + 12);
+        free(wp); free(wm);
+        t_count = g_count_on;
+        ops_flush();
     }
 done:
-    g_counting = counting;
-    free(U); free(Gp); free(Gm); free(Q); free(wp); free(wm);
+    free(U); free(Gp); free(Gm); free(Q);
     return st;
 }
 
@@ -678,10 +1011,10 @@ static int line_alphas(int nv, double gamma, long n, const double *Ul, euler_var
  * 1D Euler right-hand side L(U), U and dUdt laid out [3][n], with the
  * variant switches componentwise and per_field (not both).  alpha_out
  * (optional) receives the line's alpha, or its three per-field alphas.
+ * idx: [n+1][3][2]; ties (nullable) against a log of that layout.
  */
-int orc_euler1d_rhs_var(const orc_table *T, double gamma, int bc, long n, double ih,
-                        const double *U, double *dUdt, uint8_t *idx, double *alpha_out,
-                        int componentwise, int per_field)
+int orc_euler1d_rhs_var(const orc_table *T, double gamma, int bc, long n, double ih, const double *U, double *dUdt,
+                        uint8_t *idx, double *alpha_out, int componentwise, int per_field, orc_ties *ties)
 {
     if (!T || n < 2 || (componentwise && per_field)) return ORC_EINVAL;
     euler_var var = {componentwise != 0, per_field != 0};
@@ -692,20 +1025,24 @@ int orc_euler1d_rhs_var(const orc_table *T, double gamma, int bc, long n, double
         for (int k = 0; k < (per_field ? 3 : 1); ++k) alpha_out[k] = alpha[k];
     double *Fh = (double *)malloc(sizeof(double) * (n + 1) * 3);
     if (!Fh) return ORC_EINVAL;
-    st = euler_line_fluxes(T, 3, gamma, bc, n, U, alpha, var, Fh, idx);
-    if (!st)
+    ops_enter(ORC_OPS_X);
+    st = euler_line_fluxes(T, 3, gamma, bc, n, U, alpha, var, Fh, idx, ties, 0, 6, 1);
+    if (!st) {
         for (int v = 0; v < 3; ++v)
             for (long i = 0; i < n; ++i)
                 dUdt[v * n + i] = -((Fh[(i + 1) * 3 + v] - Fh[i * 3 + v]) * ih);
+        if (!componentwise && !per_field) OPS(2 * 3 * n);   /* the difference: sub, mul */
+    }
+    ops_flush();
     free(Fh);
     return st;
 }
 
 /* 1D Euler right-hand side L(U), U and dUdt laid out [3][n]. */
-int orc_euler1d_rhs(const orc_table *T, double gamma, int bc, long n, double ih,
-                    const double *U, double *dUdt, uint8_t *idx, double *alpha_out)
+int orc_euler1d_rhs(const orc_table *T, double gamma, int bc, long n, double ih, const double *U, double *dUdt,
+                    uint8_t *idx, double *alpha_out, orc_ties *ties)
 {
-    return orc_euler1d_rhs_var(T, gamma, bc, n, ih, U, dUdt, idx, alpha_out, 0, 0);
+    return orc_euler1d_rhs_var(T, gamma, bc, n, ih, U, dUdt, idx, alpha_out, 0, 0, ties);
 }
 
 /*
@@ -714,142 +1051,135 @@ int orc_euler1d_rhs(const orc_table *T, double gamma, int bc, long n, double ih,
  * U, dUdt: [4][ny][nx].  x-lines use (rho, m, n, E); y-lines the permuted
  * state (rho, n, m, E) so that the same normal-frame formulas apply.
  * idx_x (optional): [ny][nx+1][4][2]; idx_y (optional): [ny+1][nx][4][2].
+ * ties (nullable): against a log holding the x faces' log followed by the y
+ * faces' log, both laid out as idx_x, idx_y.
  * alpha_x[ny], alpha_y[nx] (optional) receive the per-line alphas; with
  * per_field, alpha_x[3][ny] and alpha_y[3][nx] the per-field ones.
  * componentwise, per_field (not both): the variants of the header comment;
  * gravity g != 0 adds the source g [0, 0, rho, rho v] to the result.
+ * Lines run in parallel (OpenMP); results do not depend on the thread count.
  */
-int orc_euler2d_rhs_var(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny,
-                        double ihx, double ihy, const double *U, double *dUdt,
-                        uint8_t *idx_x, uint8_t *idx_y, double *alpha_x, double *alpha_y,
-                        int componentwise, int per_field, double gravity)
+int orc_euler2d_rhs_var(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny, double ihx,
+                        double ihy, const double *U, double *dUdt, uint8_t *idx_x, uint8_t *idx_y, double *alpha_x,
+                        double *alpha_y, int componentwise, int per_field, double gravity, orc_ties *ties)
 {
     if (!T || nx < 2 || ny < 2 || (componentwise && per_field)) return ORC_EINVAL;
     euler_var var = {componentwise != 0, per_field != 0};
     const int na = per_field ? 3 : 1;
+    const int counting = !componentwise && !per_field;
     const long plane = nx * ny;
-    long nmax = nx > ny ? nx : ny;
-    double *line = (double *)malloc(sizeof(double) * 4 * nmax);
-    double *Fh = (double *)malloc(sizeof(double) * 4 * (nmax + 1));
-    uint8_t *idl = (uint8_t *)malloc(8 * (nmax + 1));
+    const int64_t nxf = (int64_t)ny * (nx + 1) * 8;
     double *Lx = (double *)malloc(sizeof(double) * 4 * plane);
     int st = ORC_OK;
-    if (!line || !Fh || !idl || !Lx) { st = ORC_EINVAL; goto done; }
+    if (!Lx) return ORC_EINVAL;
 
     /* x sweep */
-    for (long y = 0; y < ny; ++y) {
-        for (int v = 0; v < 4; ++v)
-            for (long x = 0; x < nx; ++x) line[v * nx + x] = U[v * plane + y * nx + x];
-        double alpha[3];
-        if ((st = line_alphas(4, gamma, nx, line, var, alpha))) goto done;
-        if (alpha_x)
-            for (int k = 0; k < na; ++k) alpha_x[k * ny + y] = alpha[k];
-        if ((st = euler_line_fluxes(T, 4, gamma, bcx, nx, line, alpha, var, Fh, idx_x ? idl : NULL)))
-            goto done;
-        if (idx_x) memcpy(idx_x + (size_t)y * (nx + 1) * 8, idl, (size_t)(nx + 1) * 8);
-        for (int v = 0; v < 4; ++v)
-            for (long x = 0; x < nx; ++x)
-                Lx[v * plane + y * nx + x] = -((Fh[(x + 1) * 4 + v] - Fh[x * 4 + v]) * ihx);
-        OPS(8 * nx);
-    }
-    /* y sweep on the permuted state, then combine */
-    static const int perm[4] = {0, 2, 1, 3};
-    for (long x = 0; x < nx; ++x) {
-        for (int v = 0; v < 4; ++v)
-            for (long y = 0; y < ny; ++y) line[v * ny + y] = U[perm[v] * plane + y * nx + x];
-        double alpha[3];
-        if ((st = line_alphas(4, gamma, ny, line, var, alpha))) goto done;
-        if (alpha_y)
-            for (int k = 0; k < na; ++k) alpha_y[k * nx + x] = alpha[k];
-        if ((st = euler_line_fluxes(T, 4, gamma, bcy, ny, line, alpha, var, Fh, idx_y ? idl : NULL)))
-            goto done;
-        if (idx_y)
-            for (long f = 0; f <= ny; ++f) memcpy(idx_y + ((size_t)f * nx + x) * 8, idl + f * 8, 8);
-        for (int v = 0; v < 4; ++v)
+#pragma omp parallel
+    {
+        double *line = (double *)malloc(sizeof(double) * 4 * nx);
+        double *Fh = (double *)malloc(sizeof(double) * 4 * (nx + 1));
+        uint8_t *idl = (uint8_t *)malloc(8 * (nx + 1));
+        ops_enter(ORC_OPS_X);
+        if (!line || !Fh || !idl) {
+#pragma omp atomic write
+            st = ORC_EINVAL;
+        } else {
+#pragma omp for schedule(dynamic, 4)
             for (long y = 0; y < ny; ++y) {
-                int cv = perm[v];
-                double ly = -((Fh[(y + 1) * 4 + v] - Fh[y * 4 + v]) * ihy);
-                dUdt[cv * plane + y * nx + x] = Lx[cv * plane + y * nx + x] + ly;
+                for (int v = 0; v < 4; ++v)
+                    for (long x = 0; x < nx; ++x) line[v * nx + x] = U[v * plane + y * nx + x];
+                double alpha[3];
+                int ls = line_alphas(4, gamma, nx, line, var, alpha);
+                if (!ls && alpha_x)
+                    for (int k = 0; k < na; ++k) alpha_x[k * ny + y] = alpha[k];
+                if (!ls)
+                    ls = euler_line_fluxes(T, 4, gamma, bcx, nx, line, alpha, var, Fh, idx_x ? idl : NULL, ties,
+                                           (int64_t)y * (nx + 1) * 8, 8, 0);
+                if (ls) {
+#pragma omp atomic write
+                    st = ls;
+                    continue;
+                }
+                if (idx_x) memcpy(idx_x + (size_t)y * (nx + 1) * 8, idl, (size_t)(nx + 1) * 8);
+                for (int v = 0; v < 4; ++v)
+                    for (long x = 0; x < nx; ++x)
+                        Lx[v * plane + y * nx + x] = -((Fh[(x + 1) * 4 + v] - Fh[x * 4 + v]) * ihx);
+                if (counting) OPS(2 * 4 * nx);
             }
-        OPS(12 * ny);
+        }
+        free(line); free(Fh); free(idl);
+        ops_flush();
+    }
+    if (st) goto done;
+    /* y sweep on the permuted state, then the sum */
+#pragma omp parallel
+    {
+        static const int perm[4] = {0, 2, 1, 3};
+        double *line = (double *)malloc(sizeof(double) * 4 * ny);
+        double *Fh = (double *)malloc(sizeof(double) * 4 * (ny + 1));
+        uint8_t *idl = (uint8_t *)malloc(8 * (ny + 1));
+        ops_enter(ORC_OPS_Y);
+        if (!line || !Fh || !idl) {
+#pragma omp atomic write
+            st = ORC_EINVAL;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (long x = 0; x < nx; ++x) {
+                for (int v = 0; v < 4; ++v)
+                    for (long y = 0; y < ny; ++y) line[v * ny + y] = U[perm[v] * plane + y * nx + x];
+                double alpha[3];
+                int ls = line_alphas(4, gamma, ny, line, var, alpha);
+                if (!ls && alpha_y)
+                    for (int k = 0; k < na; ++k) alpha_y[k * nx + x] = alpha[k];
+                if (!ls)
+                    ls = euler_line_fluxes(T, 4, gamma, bcy, ny, line, alpha, var, Fh, idx_y ? idl : NULL, ties,
+                                           nxf + (int64_t)x * 8, (int64_t)nx * 8, 0);
+                if (ls) {
+#pragma omp atomic write
+                    st = ls;
+                    continue;
+                }
+                if (idx_y)
+                    for (long f = 0; f <= ny; ++f) memcpy(idx_y + ((size_t)f * nx + x) * 8, idl + f * 8, 8);
+                for (int v = 0; v < 4; ++v)
+                    for (long y = 0; y < ny; ++y) {
+                        int cv = perm[v];
+                        double ly = -((Fh[(y + 1) * 4 + v] - Fh[y * 4 + v]) * ihy);
+                        dUdt[cv * plane + y * nx + x] = Lx[cv * plane + y * nx + x] + ly;
+                    }
+                if (counting) {
+                    OPS(2 * 4 * ny);               /* the difference */
+                    t_cat = ORC_OPS_SUM;
+                    OPS(4 * ny);                   /* L_x + L_y */
+                    t_cat = ORC_OPS_Y;
+                }
+            }
+        }
+        free(line); free(Fh); free(idl);
+        ops_flush();
     }
     /* source term of the Rayleigh-Taylor problem (Sec. 4.4): rho g in the
        y-momentum, rho v g in the energy equation */
-    if (gravity != 0.0)
+    if (!st && gravity != 0.0)
         for (long i = 0; i < plane; ++i) {
             dUdt[2 * plane + i] = dUdt[2 * plane + i] + gravity * U[i];
             dUdt[3 * plane + i] = dUdt[3 * plane + i] + gravity * U[2 * plane + i];
         }
 done:
-    free(line); free(Fh); free(idl); free(Lx);
+    free(Lx);
     return st;
 }
 
-int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny,
-                    double ihx, double ihy, const double *U, double *dUdt,
-                    uint8_t *idx_x, uint8_t *idx_y, double *alpha_x, double *alpha_y)
+int orc_euler2d_rhs(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny, double ihx, double ihy,
+                    const double *U, double *dUdt, uint8_t *idx_x, uint8_t *idx_y, double *alpha_x,
+                    double *alpha_y, orc_ties *ties)
 {
-    return orc_euler2d_rhs_var(T, gamma, bcx, bcy, nx, ny, ihx, ihy, U, dUdt, idx_x, idx_y, alpha_x,
-                               alpha_y, 0, 0, 0.0);
-}
-
-/*
- * L(U) at selected cells of a 2D grid only (for spot checks of large runs).
- * cells: ncell (x, y) pairs; out: [ncell][4].  Each cell needs its row's and
- * column's alpha, computed here over the whole line.
- */
-int orc_euler2d_rhs_cells(const orc_table *T, double gamma, int bcx, int bcy, long nx, long ny,
-                          double ihx, double ihy, const double *U, long ncell, const long *cells,
-                          double *out)
-{
-    if (!T || nx < 2 || ny < 2) return ORC_EINVAL;
-    const long plane = nx * ny;
-    const long w = T->r + 2;   /* cells each side needed by two faces */
-    long nmax = nx > ny ? nx : ny;
-    double *line = (double *)malloc(sizeof(double) * 4 * nmax);
-    double *seg = (double *)malloc(sizeof(double) * 4 * (2 * w + 1));
-    double *Fh = (double *)malloc(sizeof(double) * 4 * (2 * w + 2));
-    int st = ORC_OK;
-    static const int perm[4] = {0, 2, 1, 3};
-    if (!line || !seg || !Fh) { st = ORC_EINVAL; goto done; }
-    for (long q = 0; q < ncell; ++q) {
-        long cx = cells[2 * q], cy = cells[2 * q + 1];
-        double res[4];
-        for (int dir = 0; dir < 2; ++dir) {
-            long n = dir == 0 ? nx : ny;
-            long ci = dir == 0 ? cx : cy;
-            int bc = dir == 0 ? bcx : bcy;
-            for (int v = 0; v < 4; ++v)
-                for (long i = 0; i < n; ++i) {
-                    long gx = dir == 0 ? i : cx, gy = dir == 0 ? cy : i;
-                    int sv = dir == 0 ? v : perm[v];
-                    line[v * n + i] = U[sv * plane + gy * nx + gx];
-                }
-            double alpha[3] = {0.0, 0.0, 0.0};
-            if ((st = line_alpha(4, gamma, n, line, &alpha[0]))) goto done;
-            /* fluxes at the cell's two faces: evaluate on the whole line (plain) */
-            double *Fl = (double *)malloc(sizeof(double) * 4 * (n + 1));
-            if (!Fl) { st = ORC_EINVAL; goto done; }
-            st = euler_line_fluxes(T, 4, gamma, bc, n, line, alpha, k_default_var, Fl, NULL);
-            if (st) { free(Fl); goto done; }
-            for (int v = 0; v < 4; ++v) {
-                double ih = dir == 0 ? ihx : ihy;
-                double d = -((Fl[(ci + 1) * 4 + v] - Fl[ci * 4 + v]) * ih);
-                int cv = dir == 0 ? v : perm[v];
-                if (dir == 0) res[cv] = d;
-                else res[cv] = res[cv] + d;
-            }
-            free(Fl);
-        }
-        for (int v = 0; v < 4; ++v) out[q * 4 + v] = res[v];
-    }
-done:
-    free(line); free(seg); free(Fh);
-    return st;
+    return orc_euler2d_rhs_var(T, gamma, bcx, bcy, nx, ny, ihx, ihy, U, dUdt, idx_x, idx_y, alpha_x, alpha_y, 0, 0,
+                               0.0, ties);
 }
 
 /* ------------------------------------------------------------------------ */
-/* Time step and Runge-Kutta updates                                         */
+/* Time step                                                                 */
 /* ------------------------------------------------------------------------ */
 
 /* Largest |u_n| + c over a [nv][n] array of cells (normal = component 1). */
@@ -877,90 +1207,6 @@ int orc_euler2d_maxspeeds(double gamma, long nx, long ny, const double *U, doubl
     return ORC_OK;
 }
 
-/*
- * SSP-RK3 stage combination (Eq. TVD3rdRK), elementwise over n values:
- *   stage 1: out = us + dt L
- *   stage 2: out = 3/4 un + 1/4 (us + dt L)
- *   stage 3: out = 1/3 un + 2/3 (us + dt L)
- */
-void orc_ssprk3_combine(int stage, long n, const double *un, const double *us, const double *L,
-                        double dt, double *out)
-{
-    const double c13 = 1.0 / 3.0, c23 = 2.0 / 3.0;
-    for (long i = 0; i < n; ++i) {
-        double e = us[i] + dt * L[i];
-        if (stage == 1) out[i] = e;
-        else if (stage == 2) out[i] = 0.75 * un[i] + 0.25 * e;
-        else out[i] = c13 * un[i] + c23 * e;
-    }
-}
-
-/*
- * Linear SSP-RK(m, m-1) step for a scalar line (Eq. lSSPRK):
- * u^(s) = u^(s-1) + dt/2 L(u^(s-1)), s = 1..m-1, and
- * u^{n+1} = sum_{k<m-1} a_k u^(k) + a_{m-1} (u^(m-1) + dt/2 L(u^(m-1))).
- * coef holds a_0..a_{m-1} (computed exactly by the caller, Eq. lSSPRK_Coe).
- */
-int orc_scalar_lssp_run(const orc_table *T, int flux, double a, int split, int bc, long n,
-                        double ih, double dt, long nsteps, int m, const double *coef, double *u)
-{
-    if (m < 2 || m > 32) return ORC_EINVAL;
-    double *stages = (double *)malloc(sizeof(double) * n * m);
-    double *L = (double *)malloc(sizeof(double) * n);
-    double *acc = (double *)malloc(sizeof(double) * n);
-    int st = ORC_OK;
-    if (!stages || !L || !acc) { st = ORC_EINVAL; goto done; }
-    const double hdt = 0.5 * dt;
-    for (long step = 0; step < nsteps; ++step) {
-        memcpy(stages, u, sizeof(double) * n);
-        for (int s = 1; s < m; ++s) {
-            if ((st = orc_scalar_rhs(T, flux, a, split, bc, n, ih, stages + (s - 1) * n, L, NULL, NULL)))
-                goto done;
-            for (long i = 0; i < n; ++i) stages[s * n + i] = stages[(s - 1) * n + i] + hdt * L[i];
-        }
-        if ((st = orc_scalar_rhs(T, flux, a, split, bc, n, ih, stages + (m - 1) * n, L, NULL, NULL)))
-            goto done;
-        for (long i = 0; i < n; ++i) acc[i] = 0.0;
-        for (int k = 0; k < m - 1; ++k)
-            for (long i = 0; i < n; ++i) acc[i] = acc[i] + coef[k] * stages[k * n + i];
-        for (long i = 0; i < n; ++i)
-            u[i] = acc[i] + coef[m - 1] * (stages[(m - 1) * n + i] + hdt * L[i]);
-    }
-done:
-    free(stages); free(L); free(acc);
-    return st;
-}
-
-/*
- * SSP-RK3 run of a scalar line with a fixed step dt; the last step is cut so
- * that the run ends exactly at t_end (if t_end > 0, else nsteps steps).
- */
-int orc_scalar_ssprk3_run(const orc_table *T, int flux, double a, int split, int bc, long n,
-                          double ih, double dt, double t_end, long nsteps, double *u)
-{
-    double *un = (double *)malloc(sizeof(double) * n);
-    double *us = (double *)malloc(sizeof(double) * n);
-    double *L = (double *)malloc(sizeof(double) * n);
-    int st = ORC_OK;
-    if (!un || !us || !L) { st = ORC_EINVAL; goto done; }
-    double t = 0.0;
-    for (long step = 0; t_end > 0.0 ? t < t_end : step < nsteps; ++step) {
-        double h = dt;
-        if (t_end > 0.0 && t + h > t_end) h = t_end - t;
-        memcpy(un, u, sizeof(double) * n);
-        memcpy(us, u, sizeof(double) * n);
-        for (int s = 1; s <= 3; ++s) {
-            if ((st = orc_scalar_rhs(T, flux, a, split, bc, n, ih, us, L, NULL, NULL))) goto done;
-            orc_ssprk3_combine(s, n, un, us, L, h, us);
-        }
-        memcpy(u, us, sizeof(double) * n);
-        t = t + h;
-    }
-done:
-    free(un); free(us); free(L);
-    return st;
-}
-
 /* ------------------------------------------------------------------------ */
 /* Frozen-stencil 1D Euler operator with its tangent (dual numbers)          */
 /* ------------------------------------------------------------------------ */
@@ -981,11 +1227,11 @@ static dual dadd(dual a, dual b) { dual r = {a.v + b.v, a.d + b.d}; return r; }
 static dual dsub(dual a, dual b) { dual r = {a.v - b.v, a.d - b.d}; return r; }
 static dual dmul(dual a, dual b) { dual r = {a.v * b.v, a.d * b.v + a.v * b.d}; return r; }
 static dual dscale(double c, dual a) { dual r = {c * a.v, c * a.d}; return r; }
-static dual dinv(dual a) { dual r = {1.0 / a.v, -a.d / (a.v * a.v)}; return r; }
+static dual ddiv(dual a, dual b) { dual r = {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; return r; }
 static dual dsqrt(dual a) { double s = sqrt(a.v); dual r = {s, a.d / (2.0 * s)}; return r; }
 static dual dfma(dual a, dual b, dual c) { dual r = {fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d}; return r; }
 
-/* chain acc = c[0] x[0]; acc = fma(c[i], x[i], acc) */
+/* row_dot() in dual arithmetic */
 static dual ddot(const dual *c, const dual *x, int n)
 {
     dual acc = dmul(c[0], x[0]);
@@ -993,15 +1239,7 @@ static dual ddot(const dual *c, const dual *x, int n)
     return acc;
 }
 
-/* project_dot() in dual arithmetic */
-static dual dproject(const dual *c, const dual *x, int n)
-{
-    dual acc = dmul(c[n - 1], x[n - 1]);
-    for (int i = n - 2; i >= 0; --i) acc = dfma(c[i], x[i], acc);
-    return acc;
-}
-
-/* recon of one window with a frozen choice k (frame as in recon_face) */
+/* candidate_value() of a frozen choice k in dual arithmetic (frame as in recon_face) */
 static dual recon_frozen(const orc_table *T, const dual *f, long j, int sign, int k)
 {
     const int s = sign > 0 ? 1 : -1;
@@ -1009,7 +1247,8 @@ static dual recon_frozen(const orc_table *T, const dual *f, long j, int sign, in
 #define FD(l) (f[c + (long)s * (l)])
     const int m = T->m[k], n = T->n[k];
     if (m >= 1 && n >= 1) {
-        int l0 = (s > 0) ? -m : n, dl = (s > 0) ? 1 : -1, l = l0;
+        int l = (s > 0) ? -m : n;
+        const int dl = (s > 0) ? 1 : -1;
         dual acc = dmul(D(T->a[k][l + m]), FD(l));
         for (int q = 1; q < m + n + 1; ++q) {
             l += dl;
@@ -1025,23 +1264,6 @@ static dual recon_frozen(const orc_table *T, const dual *f, long j, int sign, in
     return dadd(f0, dscale(0.5, mm));
 }
 
-/* The full stencil's a_l sum of component v of the split fluxes G ([cell][3]),
-   frame and cell order as in recon_face (dual arithmetic). */
-static dual full_sum_frozen(const orc_table *T, const dual *G, long j, int sign, int v)
-{
-    const int s = sign > 0 ? 1 : -1;
-    const long c = sign > 0 ? j : j + 1;
-    const int m = T->m[0], n = T->n[0];
-    int l = (s > 0) ? -m : n;
-    const int dl = (s > 0) ? 1 : -1;
-    dual acc = dmul(D(T->a[0][l + m]), G[(c + (long)s * l) * 3 + v]);
-    for (int q = 1; q < m + n + 1; ++q) {
-        l += dl;
-        acc = dfma(D(T->a[0][l + m]), G[(c + (long)s * l) * 3 + v], acc);
-    }
-    return acc;
-}
-
 /*
  * Frozen operator and tangent: L = L(U; idx, alpha), dL = dL/dU . dU.
  * U, dU, L, dL: [3][n]; idx: [n+1][3][2] as from orc_euler1d_rhs.  dU and dL
@@ -1054,7 +1276,6 @@ int orc_euler1d_rhs_frozen(const orc_table *T, double gamma, int bc, long n, dou
     const long g = T->r + 1;
     const long nn = n + 2 * g;
     const double gm1 = gamma - 1.0;
-    dual *Uc = (dual *)malloc(sizeof(dual) * nn * 3);
     dual *Gp = (dual *)malloc(sizeof(dual) * nn * 3);
     dual *Gm = (dual *)malloc(sizeof(dual) * nn * 3);
     dual *un = (dual *)malloc(sizeof(dual) * nn);
@@ -1064,73 +1285,66 @@ int orc_euler1d_rhs_frozen(const orc_table *T, double gamma, int bc, long n, dou
     dual *wm = (dual *)malloc(sizeof(dual) * nn);
     dual *Fh = (dual *)malloc(sizeof(dual) * (n + 1) * 3);
     int st = ORC_OK;
-    if (!Uc || !Gp || !Gm || !un || !H || !sq || !wp || !wm || !Fh) { st = ORC_EINVAL; goto done; }
+    if (!Gp || !Gm || !un || !H || !sq || !wp || !wm || !Fh) { st = ORC_EINVAL; goto done; }
     for (long i = 0; i < nn; ++i) {
         long src = map_cell(i - g, n, bc);
         dual rho = {U[src], dU ? dU[src] : 0.0};
         dual mn = {U[n + src], dU ? dU[n + src] : 0.0};
         dual E = {U[2 * n + src], dU ? dU[2 * n + src] : 0.0};
-        dual ir = dinv(rho);
-        dual u = dmul(mn, ir);
+        dual u = ddiv(mn, rho);
         dual ke = dscale(0.5, dmul(mn, u));
         dual p = dscale(gm1, dsub(E, ke));
         if (!(rho.v > 0.0) || !(p.v > 0.0)) { st = ORC_ENONPHYS; goto done; }
-        dual F[3] = {mn, dadd(dmul(mn, u), p), dmul(dadd(E, p), u)};
+        dual Ep = dadd(E, p);
+        dual F[3] = {mn, dadd(dmul(mn, u), p), dmul(Ep, u)};
         dual Ucs[3] = {rho, mn, E};
         for (int v = 0; v < 3; ++v) {
             dual t = dscale(alpha, Ucs[v]);
-            Uc[i * 3 + v] = Ucs[v];
             Gp[i * 3 + v] = dscale(0.5, dadd(F[v], t));
             Gm[i * 3 + v] = dscale(0.5, dsub(F[v], t));
         }
         un[i] = u;
-        H[i] = dmul(dadd(E, p), ir);
+        H[i] = ddiv(Ep, rho);
         sq[i] = dsqrt(rho);
     }
     for (long f = 0; f <= n; ++f) {
         long j = f - 1 + g;
         /* Roe eigenvectors, the formulas of roe_eigen() in dual arithmetic */
-        dual id = dinv(dadd(sq[j], sq[j + 1]));
-        dual u = dmul(dadd(dmul(sq[j], un[j]), dmul(sq[j + 1], un[j + 1])), id);
-        dual Hr = dmul(dadd(dmul(sq[j], H[j]), dmul(sq[j + 1], H[j + 1])), id);
+        dual den = dadd(sq[j], sq[j + 1]);
+        dual u = ddiv(dadd(dmul(sq[j], un[j]), dmul(sq[j + 1], un[j + 1])), den);
+        dual Hr = ddiv(dadd(dmul(sq[j], H[j]), dmul(sq[j + 1], H[j + 1])), den);
         dual q2 = dmul(u, u);
-        dual c2 = dscale(gm1, dsub(Hr, dscale(0.5, q2)));
+        dual hq2 = dscale(0.5, q2);
+        dual c2 = dscale(gm1, dsub(Hr, hq2));
         if (!(c2.v > 0.0)) { st = ORC_ENONPHYS; goto done; }
         dual c = dsqrt(c2);
-        dual k = dscale(gm1, dinv(c2));
-        k.v = gm1 / c2.v;                     /* the forward divides once */
-        dual ic = dinv(c);
-        dual hq = dmul(dscale(0.5, k), q2);
+        dual k = ddiv(D(gm1), c2);
+        dual hk = dscale(0.5, k);
+        dual hq = dmul(hk, q2);
+        dual uic = ddiv(u, c);
+        dual ic = ddiv(D(1.0), c);
         dual ku = dmul(k, u);
-        dual uic = dmul(u, ic);
         dual uc = dmul(u, c);
         dual Lm[3][3] = {
-            {dscale(0.5, dadd(hq, uic)), dscale(-0.5, dadd(ku, ic)), dscale(0.5, k)},
+            {dscale(0.5, dadd(hq, uic)), dscale(-0.5, dadd(ku, ic)), hk},
             {dsub(D(1.0), hq), ku, dscale(-1.0, k)},
-            {dscale(0.5, dsub(hq, uic)), dscale(-0.5, dsub(ku, ic)), dscale(0.5, k)},
+            {dscale(0.5, dsub(hq, uic)), dscale(-0.5, dsub(ku, ic)), hk},
         };
         dual Rm[3][3] = {
             {D(1.0), D(1.0), D(1.0)},
             {dsub(u, c), u, dadd(u, c)},
-            {dsub(Hr, uc), dscale(0.5, q2), dadd(Hr, uc)},
+            {dsub(Hr, uc), hq2, dadd(Hr, uc)},
         };
-        /* the full stencil's flux is the projection of the a_l sums (as in
-           euler_line_fluxes) */
-        dual Ap[3], Am[3];
-        for (int v = 0; v < 3; ++v) {
-            Ap[v] = full_sum_frozen(T, Gp, j, +1, v);
-            Am[v] = full_sum_frozen(T, Gm, j, -1, v);
-        }
         dual what[3];
         for (int q = 0; q < 3; ++q) {
             for (long i = j - T->r + 1; i <= j + T->r; ++i) {
-                wp[i] = dproject(Lm[q], &Gp[i * 3], 3);
-                wm[i] = dproject(Lm[q], &Gm[i * 3], 3);
+                wp[i] = ddot(Lm[q], &Gp[i * 3], 3);
+                wm[i] = ddot(Lm[q], &Gm[i * 3], 3);
             }
             int kp = idx[(f * 3 + q) * 2 + 0], km = idx[(f * 3 + q) * 2 + 1];
             if (kp >= T->ncand || km >= T->ncand) { st = ORC_EINVAL; goto done; }
-            dual hp = kp == 0 ? dproject(Lm[q], Ap, 3) : recon_frozen(T, wp, j, +1, kp);
-            dual hm = km == 0 ? dproject(Lm[q], Am, 3) : recon_frozen(T, wm, j, -1, km);
+            dual hp = recon_frozen(T, wp, j, +1, kp);
+            dual hm = recon_frozen(T, wm, j, -1, km);
             what[q] = dadd(hp, hm);
         }
         for (int v = 0; v < 3; ++v) Fh[f * 3 + v] = ddot(Rm[v], what, 3);
@@ -1142,6 +1356,7 @@ int orc_euler1d_rhs_frozen(const orc_table *T, double gamma, int bc, long n, dou
             if (dL) dL[v * n + i] = -(d.d * ih);
         }
 done:
-    free(Uc); free(Gp); free(Gm); free(un); free(H); free(sq); free(wp); free(wm); free(Fh);
+    free(Gp); free(Gm); free(un); free(H); free(sq); free(wp); free(wm); free(Fh);
     return st;
 }
+#endif /* !ORC_QUAD */
