@@ -1,7 +1,8 @@
-"""The benchmark's algorithmic operation count (bench.sweep_ops, applied to
-stencil logs) equals the oracle's instrumented count of the same operator
-evaluation (orc_ops_begin/orc_ops_end, counted as the method's steps run, the
-early exit included).  No GPU: both sides use the oracle's own logs."""
+"""The benchmark's algorithmic operation count (bench.line_ops and
+bench.stage_tail_ops, applied to stencil logs) equals the oracle's
+instrumented count of the same operator evaluation (orc_ops_begin /
+orc_ops_end, counted as the method's steps run in the paper's order, the early
+exit included, fma = 1).  No GPU: both sides use the oracle's own logs."""
 import numpy as np
 import pytest
 
@@ -30,18 +31,29 @@ def test_log_based_count_equals_instrumented_oracle(order, bcx, bcy):
     hy_ = _field_hist(iyl)
     fx = ny * (nx if bcx == oracle.PERIODIC else nx + 1)
     fy = nx * (ny if bcy == oracle.PERIODIC else ny + 1)
-    got = bench.sweep_ops(order, fx, nx * ny, hx_, "x") + bench.sweep_ops(order, fy, nx * ny, hy_, "y")
+    ox, _ = bench.line_ops(order, fx, nx * ny, hx_)
+    oy, _ = bench.line_ops(order, fy, nx * ny, hy_)
     assert hx_[:, 1:].sum() > 0 and hy_[:, 1:].sum() > 0      # the data exercises the fallback
     assert hx_[2, 1:].sum() > 0                               # the shear field's fallback too
-    assert got == ops, (got, ops)
+    assert ox == ops[0], (ox, ops[0])
+    assert oy == ops[1], (oy, ops[1])
+    assert ops[2] == nx * ny * bench.SUM_OPS and ops[3] == 0
+
+
+def test_stage_combination_count():
+    (x, y, hx, hy), U = workloads.euler2d_quadrants_vortices(3, 20, 17)
+    L = oracle.euler2d_rhs(9, U, hx, hy)
+    for stage in (1, 2, 3):
+        cats = np.zeros(4)
+        oracle.lib().orc_ops_begin()
+        oracle.ssprk3_combine(stage, U, U, L, 1e-3)
+        oracle.lib().orc_ops_end(oracle._p(cats))
+        assert cats[3] == bench.stage_tail_ops(20 * 17, stage) - 20 * 17 * bench.SUM_OPS
+        assert cats[:3].sum() == 0
 
 
 def test_smooth_face_count_closed_form():
-    # On smooth data every reconstruction takes the full stencil (C = 0): the
-    # count per face is the Roe part, per sign five centre projections, the
-    # a_l and b_l sums of four components ((2r-1)-term chains) and their two
-    # projections, the back-projection, plus 8 times (IS0 + compare); per
-    # cell staging and difference.
+    # On smooth data every reconstruction takes the full stencil (C = 0).
     order, n = 17, 128
     r = (order + 1) // 2
     x = np.linspace(-1.0, 1.0, n, endpoint=False)
@@ -56,6 +68,13 @@ def test_smooth_face_count_closed_form():
     assert not ix.any() and not iy.any()
     ny, nx = rho.shape
     w = 2 * r - 1
-    per_face = 44 + 2 * (5 * 20 + 2 * 4 * (2 * w - 1) + 2 * 20) + 24 + 8 * (11 + 1)
-    expect = (ny * nx + nx * ny) * per_face + nx * ny * (36 + 8) + nx * ny * (36 + 12)
-    assert ops == expect
+    # per face: Roe, projection of both windows onto every field, back-projection,
+    # and 8 reconstructions of IS0 + b_l chain + compare + a_l chain
+    per_face = 42 + 2 * w * 16 + (4 + 16) + 8 * (11 + (w + 1) + w)
+    per_cell = (18 + 5 * 4) + 2 * 4       # staging and the difference, per line
+    assert ops[0] == ny * nx * per_face + nx * ny * per_cell
+    assert ops[1] == nx * ny * per_face + nx * ny * per_cell
+    assert ops[2] == nx * ny * 4
+    # about 2060 operations per cell and RK stage at order 17 (with the average stage combination)
+    total = (ops[:3].sum() + nx * ny * (8 + 20 + 20) / 3) / (nx * ny)
+    assert 2000 < total < 2100, total

@@ -1,13 +1,16 @@
 """Frozen-stencil adjoint on the GPU against the oracle's transposed Jacobians
 and against central finite differences (h = 1e-6) of runs with the recorded
-step sizes."""
+step sizes.  The reference adjoint runs along the GPU's recorded forward
+run (its stage states, stencil choices, alphas and step sizes), whose
+choices are checked against the oracle's under the near-tie rule."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads
 from adjoint_ref import adjoint as ref_adjoint
-from adjoint_ref import frozen_run, record_run
+from adjoint_ref import frozen_run
+from parity import DT_TOL, FINAL_TOL, assert_ties, check_euler1d_operator, rel_err_per_var
 
 pytestmark = pytest.mark.gpu
 
@@ -55,6 +58,35 @@ def test_rhs_adjoint_is_the_transposed_jacobian(ctx, order, n, bc):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), np.abs(got - ref).max() / np.abs(ref).max()
 
 
+def _gpu_record(ctx, prob, U0, nsteps, cfl=0.5):
+    """The GPU's recorded run as the oracle-side reference takes it:
+    [(dt, [(stage state, stencil log, alpha) x 3])], each stage's choices
+    checked against the oracle on the same stage state."""
+    import torch
+    n = prob.nx
+    ib = prob.idx_bytes()
+    stages = torch.empty((nsteps, 3, 3 * n), dtype=torch.float64, device="cuda")
+    idx = torch.empty((nsteps, 3 * ib), dtype=torch.uint8, device="cuda")
+    alpha = torch.empty((nsteps, 3), dtype=torch.float64, device="cuda")
+    dts = torch.empty((nsteps, 1), dtype=torch.float64, device="cuda")
+    U = _dev(U0)
+    ctx.record_steps(prob, U, cfl, nsteps, stages, idx, alpha, dts)
+    ctx.check()
+    S, I, A, D = stages.cpu().numpy(), idx.cpu().numpy(), alpha.cpu().numpy(), dts.cpu().numpy()
+    rec = []
+    for k in range(nsteps):
+        st = []
+        for s in range(3):
+            us = S[k, s].reshape(3, n)
+            log = I[k, s * ib:(s + 1) * ib].reshape(n + 1, 3, 2)
+            _, _, oa, rep = oracle.euler1d_rhs_follow(prob.order, us, prob.hx, log, bc=prob.bc_x)
+            assert_ties(rep, "recorded step %d stage %d" % (k, s + 1))
+            assert abs(A[k, s] - oa[0]) <= 1e-14 * oa[0]
+            st.append((us, log, float(A[k, s])))
+        rec.append((float(D[k, 0]), st))
+    return U.cpu().numpy(), rec
+
+
 def test_recorded_step_equals_plain_step(ctx):
     import torch
     import paper_2311_15504_amd as enomr
@@ -70,14 +102,14 @@ def test_recorded_step_equals_plain_step(ctx):
     ctx.advance(prob, B, 0.5, 1)
     ctx.check()
     assert torch.equal(A, B)
-    _, rec = record_run(9, U0, h, 1)
-    rdt, rst = rec[0]
-    assert dt.item() == rdt
+    assert torch.equal(stages[0].view(3, 300), _dev(U0))
+    assert abs(dt.item() - oracle.dt_1d(U0, h, 0.5)) <= DT_TOL * dt.item()
     ib = prob.idx_bytes()
     for s in range(3):
-        assert np.array_equal(stages[s].cpu().numpy().reshape(3, 300), rst[s][0])
-        assert np.array_equal(idx[s * ib:(s + 1) * ib].cpu().numpy(), rst[s][1].reshape(-1))
-        assert alpha[s].item() == rst[s][2]
+        us = stages[s].cpu().numpy().reshape(3, 300)
+        got, _ = ctx.rhs(prob, _dev(us), with_idx=True)
+        check_euler1d_operator(9, us, h, got.cpu().numpy(), idx[s * ib:(s + 1) * ib].cpu().numpy())
+        assert abs(alpha[s].item() - oracle.euler_maxspeed_1d(us)) <= 1e-14 * alpha[s].item()
 
 
 def _loss_grad_gpu(ctx, prob, U0, target, h, cfl, nsteps, every):
@@ -102,10 +134,12 @@ def test_gradient_matches_oracle_adjoint_and_fd(ctx, bc):
     target = workloads.density_target(4, n)
     prob = enomr.Problem.euler1d(n, h, order, bc=bc)
     Jv, g, UT = _loss_grad_gpu(ctx, prob, U0, target, h, 0.5, nsteps, every)
-    UT_ref, rec = record_run(order, U0, h, nsteps, bc=bc)
-    assert np.abs(UT - UT_ref).max() <= 1e-10 * max(1.0, np.abs(UT_ref).max())
+    UT_rec, rec = _gpu_record(ctx, prob, U0, nsteps)
+    assert np.array_equal(UT, UT_rec)
+    # the oracle's frozen run with the recorded choices reproduces the GPU run
+    assert max(rel_err_per_var(frozen_run(order, U0, h, rec, bc=bc), UT, floor=1.0)) <= FINAL_TOL
     lamT = np.zeros_like(U0)
-    lamT[0] = 2.0 * h * (UT_ref[0] - target)
+    lamT[0] = 2.0 * h * (UT[0] - target)
     g_ref = ref_adjoint(order, h, rec, lamT, bc=bc).reshape(U0.shape)
     assert np.abs(g - g_ref).max() <= 1e-10 * np.abs(g_ref).max()
     # central differences of the frozen run

@@ -1,11 +1,14 @@
 """Batched persistent execution (one hipGraph-replayed launch for many 1D
-Euler problems of uneven sizes and orders): each problem equals its
-single-problem run bit for bit, and the oracle to the final-time tolerance."""
+and 2D Euler problems of uneven sizes and orders): each problem equals its
+single-problem run bit for bit, and the oracle's run that follows the
+single-problem run's stencil choices at the ties (tests/parity.py) to the
+final-time tolerance."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads
+from parity import FINAL_TOL, follow_run_1d, follow_run_2d, host, rel_err_per_var
 
 pytestmark = pytest.mark.gpu
 
@@ -151,6 +154,8 @@ def test_batch_graph_replays_each_match_eager_runs(ctx):
 
 
 def test_batch_matches_oracle(ctx):
+    # Each problem's batched result equals its logged single-problem run bit
+    # for bit, and that run is checked stage by stage against the oracle.
     import torch
     import paper_2311_15504_amd as enomr
     probs, data = _problems(6, 2)
@@ -160,10 +165,46 @@ def test_batch_matches_oracle(ctx):
     batch.advance(0.5, 10)
     ctx.check()
     for p, U0, Ub in zip(probs, data, states):
-        ref, _ = oracle.euler1d_run(p.order, U0, p.hx, 10, cfl=0.5, bc=p.bc_x)
-        got = Ub.cpu().numpy()
-        assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+        got, ref, _, _ = follow_run_1d(ctx, p, U0, 10, what="batched 1D problem")
+        assert np.array_equal(host(Ub), got)
+        assert max(rel_err_per_var(host(Ub), ref, floor=1.0)) <= FINAL_TOL
     batch.close()
+
+
+def test_batch_2d_matches_oracle_every_order_bc_and_tile_shape(ctx):
+    # 2D problems of uneven sizes at every order 5..17 and every boundary
+    # combination, in one batch, for each tile shape of the 2D kernel: every
+    # final state within the final-time tolerance of the oracle's run (which
+    # follows the logged single-problem run's choices at the ties).
+    import torch
+    import paper_2311_15504_amd as enomr
+    rng = np.random.default_rng(21)
+    bcs = [(enomr.PERIODIC, enomr.OUTFLOW), (enomr.OUTFLOW, enomr.PERIODIC), (enomr.OUTFLOW, enomr.OUTFLOW),
+           (enomr.PERIODIC, enomr.PERIODIC)]
+    probs, data, refs = [], [], []
+    nsteps = 4
+    for i, order in enumerate((5, 7, 9, 11, 13, 15, 17)):
+        r = (order + 1) // 2
+        nx = int(rng.integers(2 * r + 1, 90))
+        ny = int(rng.integers(2 * r + 1, 70))
+        (x, y, hx, hy), U = workloads.euler2d_quadrants_vortices(300 + i, nx, ny)
+        bcx, bcy = bcs[i % 4]
+        p = enomr.Problem.euler2d(nx, ny, hx, hy, order, bcx, bcy)
+        got, ref, _, _ = follow_run_2d(ctx, p, U, nsteps, what="batched 2D problem", bcx=bcx, bcy=bcy)
+        probs.append(p)
+        data.append(U)
+        refs.append((got, ref))
+    for shape in ((64, 4), (32, 8), (16, 16)):
+        states = [torch.from_numpy(U).cuda() for U in data]
+        batch = enomr.Batch(ctx, probs, states, autotune=False)
+        batch.set_tile2d(*shape)
+        batch.advance(0.5, nsteps)
+        ctx.check()
+        for p, Ub, (got, ref) in zip(probs, states, refs):
+            assert np.array_equal(host(Ub), got), (shape, p.order)
+            err = max(rel_err_per_var(host(Ub), ref, floor=1.0))
+            assert err <= FINAL_TOL, (shape, p.order, p.nx, p.ny, p.bc_x, p.bc_y, err)
+        batch.close()
 
 
 def test_batch_full_workload_sampled(ctx):
@@ -171,7 +212,7 @@ def test_batch_full_workload_sampled(ctx):
     # orders {7, 9, 13, 17}, 100 steps in one graph launch with the autotuned
     # tile width.  A seeded sample (with the longest and the shortest problem)
     # equals its single-problem runs bit for bit, and the three shortest of the
-    # sample equal the oracle to the final-time tolerance.
+    # sample are checked stage by stage against the oracle.
     import torch
     import paper_2311_15504_amd as enomr
     nsteps = 100
@@ -191,10 +232,8 @@ def test_batch_full_workload_sampled(ctx):
         ctx.check()
         assert torch.equal(U, states[i]), (i, plist[i]["n"], plist[i]["order"])
     for i in sorted(sample, key=lambda k: ns[k])[:3]:
-        p = plist[i]
-        ref, _ = oracle.euler1d_run(p["order"], p["U"], p["h"], nsteps, cfl=0.5)
-        got = states[i].cpu().numpy()
-        assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max()), (i, p["n"], p["order"])
+        got, ref, _, _ = follow_run_1d(ctx, probs[i], plist[i]["U"], nsteps, what="batched workload problem")
+        assert np.array_equal(host(states[i]), got), (i, plist[i]["n"], plist[i]["order"])
     batch.close()
 
 

@@ -1,11 +1,13 @@
 """Parity of the Euler operator variants on the GPU with the oracle:
 component-wise reconstruction, per-field alphas and the gravity source of the
-Rayleigh-Taylor problem (Sec. 4.4).  Stencil logs and operators bitwise."""
+Rayleigh-Taylor problem (Sec. 4.4), under the near-tie rule of
+tests/parity.py."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads
+from parity import check_euler1d_operator, check_euler2d_operator, follow_run_2d
 
 pytestmark = pytest.mark.gpu
 
@@ -34,33 +36,26 @@ def _host(t):
 
 @pytest.mark.parametrize("kw", VARIANTS, ids=["componentwise", "per_field"])
 @pytest.mark.parametrize("order", [5, 9, 13, 17])
-def test_euler1d_variant_operator_bitwise(ctx, order, kw):
+def test_euler1d_variant_operator(ctx, order, kw):
     import paper_2311_15504_amd as enomr
     n = 1000
     _, h, U = workloads.euler1d_riemann_perturbed(order + 100, n)
     for bc in (enomr.OUTFLOW, enomr.PERIODIC):
-        ref, ridx, _ = oracle.euler1d_rhs_var(order, U, h, bc=bc, **kw)
         got, gidx = ctx.rhs(enomr.Problem.euler1d(n, h, order, bc=bc, **kw), _dev(U), with_idx=True)
         ctx.check()
-        assert np.array_equal(_host(gidx).reshape(-1, 3, 2), ridx)
-        assert np.array_equal(_host(got), ref)
+        check_euler1d_operator(order, U, h, _host(got), _host(gidx), what=str(kw), bc=bc, **kw)
 
 
 @pytest.mark.parametrize("kw", VARIANTS + [dict(gravity=1.0), dict(per_field=True, gravity=-0.5)],
                          ids=["componentwise", "per_field", "gravity", "per_field_gravity"])
 @pytest.mark.parametrize("order", [5, 9, 13, 17])
-def test_euler2d_variant_operator_bitwise(ctx, order, kw):
+def test_euler2d_variant_operator(ctx, order, kw):
     import paper_2311_15504_amd as enomr
     nx, ny = 150, 70                                   # ragged against both tile shapes
     (x, y, hx, hy), U = workloads.euler2d_quadrants_vortices(order + 7, nx, ny)
-    ref, ix, iy, _, _ = oracle.euler2d_rhs_var(order, U, hx, hy, **kw)
     got, gidx = ctx.rhs(enomr.Problem.euler2d(nx, ny, hx, hy, order, **kw), _dev(U), with_idx=True)
     ctx.check()
-    gidx = _host(gidx)
-    nxf = ny * (nx + 1) * 8
-    assert np.array_equal(gidx[:nxf].reshape(ny, nx + 1, 4, 2), ix)
-    assert np.array_equal(gidx[nxf:].reshape(ny + 1, nx, 4, 2), iy)
-    assert np.array_equal(_host(got), ref)
+    check_euler2d_operator(order, U, hx, hy, _host(got), _host(gidx), what=str(kw), **kw)
 
 
 @pytest.mark.parametrize("kw", VARIANTS, ids=["componentwise", "per_field"])
@@ -69,46 +64,34 @@ def test_smallest_periodic_grid_variants(ctx, kw):
     order = 17
     n = order + 2
     (x, y, hx, hy), U = workloads.euler2d_quadrants_vortices(5, n, n)
-    ref = oracle.euler2d_rhs_var(order, U, hx, hy, bcx=oracle.PERIODIC, bcy=oracle.PERIODIC, **kw)[0]
-    got = ctx.rhs(enomr.Problem.euler2d(n, n, hx, hy, order, enomr.PERIODIC, enomr.PERIODIC, **kw), _dev(U))
+    got, gidx = ctx.rhs(enomr.Problem.euler2d(n, n, hx, hy, order, enomr.PERIODIC, enomr.PERIODIC, **kw), _dev(U),
+                        with_idx=True)
     ctx.check()
-    assert np.array_equal(_host(got), ref)
+    check_euler2d_operator(order, U, hx, hy, _host(got), _host(gidx), what=str(kw), bcx=oracle.PERIODIC,
+                           bcy=oracle.PERIODIC, **kw)
 
 
 @pytest.mark.parametrize("order", [5, 9])
 def test_rayleigh_taylor_run_matches_oracle(ctx, order):
     # The Rayleigh-Taylor data with its gravity source, x periodic (the
     # perturbation has period 1/4), y outflow; 6 SSP-RK3 steps.
-    import torch
     import paper_2311_15504_amd as enomr
     g53 = 5.0 / 3.0
     nx, ny = 32, 128
     (x, y, hx, hy), U0 = workloads.euler2d_rayleigh_taylor(nx, ny, g53)
-    ref, dts = oracle.euler2d_run(order, U0, hx, hy, 6, cfl=0.5, gamma=g53, gravity=1.0)
     prob = enomr.Problem.euler2d(nx, ny, hx, hy, order, enomr.PERIODIC, enomr.OUTFLOW, gamma=g53, gravity=1.0)
-    U = _dev(U0)
-    dt_log = torch.zeros(6, dtype=torch.float64, device="cuda")
-    ctx.advance(prob, U, 0.5, 6, dt_log=dt_log)
-    ctx.check()
-    assert np.array_equal(_host(dt_log), np.array(dts))
-    assert np.array_equal(_host(U), ref)
+    follow_run_2d(ctx, prob, U0, 6, what="Rayleigh-Taylor run", gamma=g53, gravity=1.0)
 
 
 def test_per_field_run_and_dt_match_oracle(ctx):
-    import torch
     import paper_2311_15504_amd as enomr
     nx, ny = 48, 40
     (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(11, nx, ny)
-    ref, dts = oracle.euler2d_run(13, U0, hx, hy, 4, cfl=0.5, per_field=True)
-    ref_line, dts_line = oracle.euler2d_run(13, U0, hx, hy, 1, cfl=0.5)
-    assert dts[0] == dts_line[0]          # the per-field maxima give the same step
+    # the per-field maxima give the same step as the line maxima
+    assert oracle.euler2d_run(13, U0, hx, hy, 1, cfl=0.5, per_field=True)[1] == \
+        oracle.euler2d_run(13, U0, hx, hy, 1, cfl=0.5)[1]
     prob = enomr.Problem.euler2d(nx, ny, hx, hy, 13, per_field=True)
-    U = _dev(U0)
-    dt_log = torch.zeros(4, dtype=torch.float64, device="cuda")
-    ctx.advance(prob, U, 0.5, 4, dt_log=dt_log)
-    ctx.check()
-    assert np.array_equal(_host(dt_log), np.array(dts))
-    assert np.array_equal(_host(U), ref)
+    follow_run_2d(ctx, prob, U0, 4, what="per-field run", per_field=True)
 
 
 def test_variants_are_rejected_where_unsupported(ctx):

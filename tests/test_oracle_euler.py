@@ -185,15 +185,6 @@ def test_2d_operator_reaches_design_order_on_diagonal_wave(order, n0):
     assert rate > order - 0.5, (errs, rate)
 
 
-def test_sampled_cells_equal_full_operator():
-    _, U = workloads.euler2d_quadrants_vortices(4, 40, 32, nvort=3)
-    L = oracle.euler2d_rhs(9, U, 0.05, 0.0625, G, oracle.PERIODIC, oracle.OUTFLOW)
-    cells = [(0, 0), (39, 31), (17, 5), (3, 30)]
-    got = oracle.euler2d_rhs_cells(9, U, 0.05, 0.0625, cells, G, oracle.PERIODIC, oracle.OUTFLOW)
-    for k, (x, y) in enumerate(cells):
-        assert np.array_equal(got[k], L[:, y, x])
-
-
 def test_lax_shock_tube_runs_and_stays_physical():
     x, h, U0 = workloads.euler1d_lax(200)
     for order in (5, 17):
