@@ -58,6 +58,15 @@
  * run in parallel over independent lines (faces) with OpenMP; every value is
  * computed by the same operations whatever the thread count.
  */
+/*
+ * ORC_PLANT (test builds only, 0 otherwise): a numbered, deliberate mistake
+ * compiled into a scratch copy of the oracle, so that a test can show that
+ * the pins catch it.  The shipped library is built with none.
+ */
+#ifndef ORC_PLANT
+#define ORC_PLANT 0
+#endif
+
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -75,6 +84,8 @@ typedef __float128 real;
 /* at 113 significant bits the fusion of a product into a sum is immaterial */
 #define R_FMA(a, b, c) ((a) * (b) + (c))
 #define ORC_FN(name) name##_q
+/* faces per line from which a scalar line's faces run in parallel */
+#define ORC_PAR_FACES 64
 #else
 typedef double real;
 #define R_ABS(x) fabs(x)
@@ -82,6 +93,7 @@ typedef double real;
 #define R_MIN(a, b) fmin(a, b)
 #define R_FMA(a, b, c) fma(a, b, c)
 #define ORC_FN(name) name
+#define ORC_PAR_FACES 4096
 #endif
 
 /* ------------------------------------------------------------------------ */
@@ -284,9 +296,13 @@ __attribute__((unused)) static real candidate_value(const orc_table *T, const re
 #ifndef ORC_QUAD
 /*
  * Where the magnitude A_l that rounding acts on comes from (see tie_margin):
- * |f_l| (row NULL), or sum_i |row_i| |G_i| over the cell's conserved
- * components (nv values at G + l * nv), or, with per-field alphas,
- * (sum_i |row_i| |F_i| + ak sum_i |row_i| |U_i|) / 2.
+ * |f_l| for a scalar law (ms NULL); for a system, every conserved component
+ * of a cell carries rounding errors at the size of the cell's largest split
+ * flux (each is updated from fluxes that include the pressure, so even a
+ * component that is zero in exact arithmetic, a symmetric shear, holds
+ * rounding noise of that size), so A_l = (sum_i |row_i|) max_i |G_i| (row
+ * NULL: the component itself, sum = 1), or with per-field alphas
+ * (sum_i |row_i|) (max_i |F_i| + ak max_i |U_i|) / 2.
  */
 typedef struct {
     const double *row;
@@ -299,15 +315,18 @@ typedef struct {
 
 static double mag_at(const mag_src *ms, const double *f, long i)
 {
-    if (!ms || !ms->row) return fabs(f[i]);
-    double a = 0.0;
-    for (int k = 0; k < ms->nv; ++k) a += fabs(ms->row[k]) * fabs(ms->G[i * ms->nv + k]);
-    if (ms->F) {
-        double b = 0.0;
-        for (int k = 0; k < ms->nv; ++k) b += fabs(ms->row[k]) * fabs(ms->F[i * ms->fstride + k]);
-        a = 0.5 * (b + ms->ak * a);
+    if (!ms) return fabs(f[i]);
+    double rs = ms->row ? 0.0 : 1.0, gm = 0.0;
+    for (int k = 0; k < ms->nv; ++k) {
+        if (ms->row) rs += fabs(ms->row[k]);
+        gm = fmax(gm, fabs(ms->G[i * ms->nv + k]));
     }
-    return a;
+    if (ms->F) {
+        double fm = 0.0;
+        for (int k = 0; k < ms->nv; ++k) fm = fmax(fm, fabs(ms->F[i * ms->fstride + k]));
+        return 0.5 * rs * (fm + ms->ak * gm);
+    }
+    return rs * gm;
 }
 
 /*
@@ -320,9 +339,8 @@ static double mag_at(const mag_src *ms, const double *f, long i)
  *   - both chose minmod branches (Step 3.2): mu = min(|da|, |db|) / S if one
  *     took the zero branch (the sign test decided), else (|da| - |db|) / S,
  *     with da, db the two slopes and S = A_{c+1} + 2 A_c + A_{c-1}.
- * A_l is the magnitude that rounding acts on when f_l is formed: |f_l| for a
- * scalar law, sum_i |l_ki| |G_i| for a projected value.  An invalid other
- * choice gives +infinity.
+ * A_l is the magnitude that rounding acts on when f_l is formed (mag_at).
+ * An invalid other choice gives +infinity.
  */
 #define AR(l) mag_at(ms, f, c + (long)s * (l))
 static double tie_margin(const orc_table *T, const double *f, const mag_src *ms, long c, int s, int own, int other,
@@ -371,7 +389,7 @@ static real recon_face(const orc_table *T, const real *f, const void *msv, long 
                        void *tiesv, int64_t pos)
 {
     const int s = sign > 0 ? 1 : -1;
-    const long c = sign > 0 ? j : j + 1;
+    const long c = (sign > 0 || ORC_PLANT == 1) ? j : j + 1;
     const int nfull = T->ncand - 3;   /* candidates 0 .. nfull-1 have m, n >= 1 */
 #ifndef ORC_QUAD
     orc_ties *ties = (orc_ties *)tiesv;
@@ -384,7 +402,7 @@ static real recon_face(const orc_table *T, const real *f, const void *msv, long 
     const real f0 = FR(0), fm1 = FR(-1), fm2 = FR(-2), fp1 = FR(1), fp2 = FR(2);
     const real isl = R_MAX(R_ABS(f0 - fm1), R_ABS((f0 - (real)2 * fm1) + fm2));
     const real isr = R_MAX(R_ABS(f0 - fp1), R_ABS((f0 - (real)2 * fp1) + fp2));
-    const real is0 = R_MIN(isl, isr);
+    const real is0 = ORC_PLANT == 2 ? R_MAX(isl, isr) : R_MIN(isl, isr);
     OPS(11);   /* two sides of (sub, mul, sub, add, max), then min */
 
     /* Steps 2 and 3.1: the indicators of the candidates with m, n >= 1 in list
@@ -396,9 +414,9 @@ static real recon_face(const orc_table *T, const real *f, const void *msv, long 
     for (int k = 0; k < nfull; ++k) {
         is[k] = R_ABS(stencil_dot(T->b[k], T->m[k], T->n[k], f, c, s));
         OPS(T->m[k] + T->n[k] + 1 + 1);   /* b_l chain and the compare */
-        if (is[k] < is0) {
+        if (ORC_PLANT == 3 ? is[k] <= is0 : is[k] < is0) {
             own = k;
-            break;
+            if (ORC_PLANT != 4) break;
         }
     }
     real out;
@@ -413,7 +431,7 @@ static real recon_face(const orc_table *T, const real *f, const void *msv, long 
         real mm;
         int pm, pn;
         if (da * db > (real)0) {
-            if (R_ABS(da) <= R_ABS(db)) { mm = da; pm = 0; pn = 1; }
+            if (ORC_PLANT == 5 ? R_ABS(da) > R_ABS(db) : R_ABS(da) <= R_ABS(db)) { mm = da; pm = 0; pn = 1; }
             else { mm = db; pm = 1; pn = 0; }
         } else {
             mm = (real)0; pm = 0; pn = 0;
@@ -519,7 +537,7 @@ int ORC_FN(orc_scalar_rhs)(const orc_table *T, int flux, real a, int split, int 
             fm[i] = 0;
         }
     }
-#pragma omp parallel if (n >= 4096)
+#pragma omp parallel if (n >= ORC_PAR_FACES)
     {
     ops_off();   /* the operation count covers the Euler operator */
 #pragma omp for schedule(static)
@@ -737,7 +755,7 @@ static int roe_eigen(int nv, double gamma, const cell_prim *qL, const cell_prim 
 {
     const double sL = qL->sq, sR = qR->sq;
     const double den = sL + sR;
-    const double u = (sL * qL->un + sR * qR->un) / den;
+    const double u = ORC_PLANT == 6 ? 0.5 * (qL->un + qR->un) : (sL * qL->un + sR * qR->un) / den;
     const double v = nv == 4 ? (sL * qL->ut + sR * qR->ut) / den : 0.0;
     const double H = (sL * qL->H + sR * qR->H) / den;
     const double q2 = nv == 4 ? u * u + v * v : u * u;
@@ -758,7 +776,7 @@ static int roe_eigen(int nv, double gamma, const cell_prim *qL, const cell_prim 
         const double kv = k * v;
         const double lv = -0.5 * kv;
         const double L[4][4] = {
-            {0.5 * (hq + uic), -0.5 * (ku + ic), lv, hk},
+            {0.5 * (hq + uic), (ORC_PLANT == 7 ? 0.5 : -0.5) * (ku + ic), lv, hk},
             {1.0 - hq, ku, kv, -k},
             {-v, 0.0, 1.0, 0.0},
             {0.5 * (hq - uic), -0.5 * (ku - ic), lv, hk},
@@ -903,7 +921,7 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
         for (int v = 0; v < nv; ++v) {
             double t = alpha[0] * U[i * nv + v];
             Gp[i * nv + v] = 0.5 * (Q[i].F[v] + t);
-            Gm[i * nv + v] = 0.5 * (Q[i].F[v] - t);
+            Gm[i * nv + v] = ORC_PLANT == 8 ? 0.5 * (Q[i].F[v] + t) : 0.5 * (Q[i].F[v] - t);
         }
         /* once per cell of the line: the primitives and fluxes, and the split
            (t, the sum and the difference, two halvings: 5 per component) */
@@ -934,8 +952,9 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
                         }
                         int kp, km;
                         const int64_t pk = pos0 + f * fstride + 2 * k;
-                        double hp = recon_face(T, wp, NULL, j, +1, &kp, ties, pk);
-                        double hm = recon_face(T, wm, NULL, j, -1, &km, ties, pk + 1);
+                        const mag_src msp = {NULL, Gp, NULL, 0, 0.0, nv}, msm = {NULL, Gm, NULL, 0, 0.0, nv};
+                        double hp = recon_face(T, wp, &msp, j, +1, &kp, ties, pk);
+                        double hm = recon_face(T, wm, &msm, j, -1, &km, ties, pk + 1);
                         Fhat[f * nv + k] = hp + hm;
                         if (idx) {
                             idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
@@ -971,15 +990,16 @@ static int euler_line_fluxes(const orc_table *T, int nv, double gamma, int bc, l
                         msp.ak = msm.ak = ak;
                     } else {
                         for (long i = j - T->r + 1; i <= j + T->r; ++i) {
-                            wp[i] = row_dot(Lm[k], &Gp[i * nv], nv);
-                            wm[i] = row_dot(Lm[k], &Gm[i * nv], nv);
+                            const int kr = ORC_PLANT == 9 ? (k + 1) % nv : k;
+                            wp[i] = row_dot(Lm[kr], &Gp[i * nv], nv);
+                            wm[i] = row_dot(Lm[kr], &Gm[i * nv], nv);
                         }
                     }
                     int kp, km;
                     const int64_t pk = pos0 + f * fstride + 2 * k;
                     double hp = recon_face(T, wp, &msp, j, +1, &kp, ties, pk);
                     double hm = recon_face(T, wm, &msm, j, -1, &km, ties, pk + 1);
-                    what[k] = hp + hm;
+                    what[k] = ORC_PLANT == 10 ? hp : hp + hm;
                     if (idx) {
                         idx[(f * nv + k) * 2 + 0] = (uint8_t)kp;
                         idx[(f * nv + k) * 2 + 1] = (uint8_t)km;
