@@ -147,6 +147,22 @@ enomr_status enomr_rhs(enomr_ctx *ctx, const enomr_problem *prob, const double *
                        double *dUdt, uint8_t *idx, void *ws);
 
 /*
+ * enomr_rhs without a workspace and without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same operator and log layout as
+ * enomr_rhs.  The per-line alphas live in a library-owned device array of
+ * 131072 doubles (1 MiB) per device, held until the process ends: a problem
+ * needs ceil32(na * ny) + na * (2D ? nx : 1) doubles of it (na = 3 with
+ * per-field alphas, else 1); a larger one is ENOMR_EINVAL with a message.  In
+ * 2D, dUdt also holds the y sweep's part of L until the x sweep completes it
+ * in place, so dUdt must not alias U (ENOMR_EINVAL).  Every call on a device
+ * shares its array: calls that overlap on one device (other streams or
+ * threads) race; calls ordered on one stream do not.
+ */
+enomr_status enomr_rhs_noalloc(enomr_ctx *ctx, const enomr_problem *prob, const double *U, double *dUdt,
+                               uint8_t *idx);
+
+/*
  * Time step from the CFL rule, written to the device scalar *dt_dev:
  *   1D: dt = cfl / (max(|u|+c) / hx), scalar laws use max|f'(u)|;
  *   2D: dt = cfl / (max(|u|+c)/hx + max(|v|+c)/hy).

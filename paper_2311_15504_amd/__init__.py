@@ -97,6 +97,7 @@ def lib():
             "enomr_recon_faces": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _vp, _vp, _vp], st),
             "enomr_workspace_size": ([P, ctypes.POINTER(ctypes.c_size_t)], st),
             "enomr_rhs": ([_vp, P, _vp, _vp, _vp, _vp], st),
+            "enomr_rhs_noalloc": ([_vp, P, _vp, _vp, _vp], st),
             "enomr_dt": ([_vp, P, _vp, ctypes.c_double, _vp, _vp], st),
             "enomr_ssprk3_step": ([_vp, P, _vp, _vp, _vp, _vp], st),
             "enomr_advance": ([_vp, P, _vp, ctypes.c_double, ctypes.c_int64, ctypes.c_double, _vp, _vp], st),
@@ -211,6 +212,17 @@ class Context:
         idx = t.empty(prob.idx_bytes(), dtype=t.uint8, device=self.device) if with_idx else None
         self._sync_stream()
         _call("enomr_rhs", self.handle, ctypes.byref(prob), _ptr(U), _ptr(out), _ptr(idx), _ptr(self.workspace(prob)))
+        return (out, idx) if with_idx else out
+
+    def rhs_noalloc(self, prob, U, with_idx=False):
+        """L(U) through enomr_rhs_noalloc (no workspace, no device allocation
+        inside the library); the output tensor is allocated here."""
+        t = self.torch
+        self._check_state(prob, U)
+        out = t.empty_like(U)
+        idx = t.empty(prob.idx_bytes(), dtype=t.uint8, device=self.device) if with_idx else None
+        self._sync_stream()
+        _call("enomr_rhs_noalloc", self.handle, ctypes.byref(prob), _ptr(U), _ptr(out), _ptr(idx))
         return (out, idx) if with_idx else out
 
     def dt(self, prob, U, cfl):

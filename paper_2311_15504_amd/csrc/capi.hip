@@ -18,6 +18,14 @@ namespace enomr {
 __constant__ double c_a[kPool][kMaxW];
 __constant__ double c_wa[2][kPool][kMaxW];
 __constant__ int c_candpool[10][kPool];
+
+// Device memory of enomr_rhs_noalloc, the entry point that allocates nothing:
+// the per-line alphas of one operator evaluation.  Each device the library
+// runs on holds its own copy until the process ends.  Host code never uses
+// this name as an address: enomr_create takes the device address with
+// hipGetSymbolAddress, per context (a context belongs to one device).
+constexpr size_t kScratchDoubles = 131072;   // 1 MiB
+__device__ __align__(256) double scratch[kScratchDoubles];
 }  // namespace enomr
 
 using namespace enomr;
@@ -28,6 +36,7 @@ struct enomr_ctx {
     int device;
     hipStream_t stream;
     unsigned* status;   // device word, latched non-physical flag
+    double* scratch;    // device address of enomr::scratch on this device
     // kernel timing (enomr_profile_start/stop): HIP event pairs per class
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[PROF_CLASSES];
@@ -223,19 +232,45 @@ constexpr int kMaxLsspStages = 18;        // linear SSP-RK(m, m-1): m up to orde
 constexpr int kTFx = 64, kTLx = 4;        // 2D x sweep
 constexpr int kTFy = 64, kTLy = 4;        // 2D y sweep
 
-// Alphas of every line of `Us` into ws (zeroed first).
-enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* Us, void* ws,
-                          const int* active)
+// Where the per-line alphas of one operator evaluation live: ay follows ax,
+// so one fill of nfill doubles from ax clears both (and the padding between).
+struct AlphaBufs {
+    double* ax;
+    double* ay;
+    long nfill;
+};
+
+long alpha_count_x(const enomr_problem& p) { return (p.alpha_mode == ENOMR_ALPHA_FIELD ? 3 : 1) * (long)p.ny; }
+long alpha_count_y(const enomr_problem& p)
+{
+    return (p.alpha_mode == ENOMR_ALPHA_FIELD ? 3 : 1) * (long)(p.ndim == 2 ? p.nx : 1);
+}
+
+AlphaBufs alpha_bufs(const enomr_problem& p, void* ws)
 {
     const Layout w = layout(p);
-    double* ax = at<double>(ws, w.ax);
-    double* ay = at<double>(ws, w.ay);
+    return AlphaBufs{at<double>(ws, w.ax), at<double>(ws, w.ay),
+                     (long)(w.ay - w.ax) / (long)sizeof(double) + alpha_count_y(p)};
+}
+
+// The same two arrays packed from `base` (256-byte aligned), for
+// enomr_rhs_noalloc; doubles_needed() is their extent.
+long alpha_ax_extent(const enomr_problem& p) { return (alpha_count_x(p) + 31) & ~31L; }
+long doubles_needed(const enomr_problem& p) { return alpha_ax_extent(p) + alpha_count_y(p); }
+AlphaBufs alpha_bufs_at(const enomr_problem& p, double* base)
+{
+    return AlphaBufs{base, base + alpha_ax_extent(p), doubles_needed(p)};
+}
+
+// Alphas of every line of `Us` into ab (zeroed first).
+enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* Us, const AlphaBufs& ab,
+                          const int* active)
+{
+    double* ax = ab.ax;
+    double* ay = ab.ay;
     const bool pf = p.alpha_mode == ENOMR_ALPHA_FIELD;
-    const long na = pf ? 3 : 1;
-    const long nax = na * p.ny, nay = na * (p.ndim == 2 ? p.nx : 1);
     timed(ctx, PROF_AUX, [&] {
-        // ay follows ax in the workspace: one fill clears both (and the padding between)
-        const long nfill = (long)(w.ay - w.ax) / (long)sizeof(double) + nay;
+        const long nfill = ab.nfill;
         hipLaunchKernelGGL(k_fill, dim3(blocks_for(nfill, 256)), dim3(256), 0, ctx->stream, ax, nfill, 0.0);
         if (p.system == ENOMR_EULER) {
             dim3 grid(blocks_for(p.nx, 64), blocks_for(p.ny, 32));
@@ -261,14 +296,20 @@ enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* 
     return ENOMR_OK;
 }
 
-// The operator L(Us) and its use: stage 0 stores L into so.out, stages 1..3
-// combine the SSP-RK3 stage.  Requires the alphas of Us in ws.
-enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const double* Us, StageOut so,
-                             uint8_t* idx, void* ws, const int* active)
+enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* Us, void* ws, const int* active)
 {
-    const Layout w = layout(p);
-    const double* ax = at<double>(ws, w.ax);
-    const double* ay = at<double>(ws, w.ay);
+    return launch_alpha(ctx, p, Us, alpha_bufs(p, ws), active);
+}
+
+// The operator L(Us) and its use: stage 0 stores L into so.out, stages 1..3
+// combine the SSP-RK3 stage.  Requires the alphas of Us in ab.  2D: the y
+// sweep stores L_y into Ly, which the x sweep reads back cell by cell (each
+// thread reads and writes only its own cells, so Ly may be so.out).
+enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const double* Us, StageOut so,
+                             uint8_t* idx, const AlphaBufs& ab, double* Ly, const int* active)
+{
+    const double* ax = ab.ax;
+    const double* ay = ab.ay;
     if (p.system != ENOMR_EULER) {
         const int flux = p.system == ENOMR_ADVECTION ? SYS_ADVECTION : SYS_BURGERS;
         const int split = p.split == ENOMR_SPLIT_LF ? 1 : 0;
@@ -311,11 +352,10 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
         HIP_TRY(hipGetLastError());
         return ENOMR_OK;
     }
-    // 2D: the y sweep stores L_y into the workspace, then the x sweep adds
-    // L_x (L_y + L_x = L_x + L_y exactly) and the source, and either stores
-    // the sum or combines the RK stage: the output phase with its extra reads
-    // runs in the sweep whose lines are rows, so those reads are coalesced.
-    double* Ly = at<double>(ws, w.L);
+    // 2D: the y sweep stores L_y, then the x sweep adds L_x (L_y + L_x =
+    // L_x + L_y exactly) and the source, and either stores the sum or combines
+    // the RK stage: the output phase with its extra reads runs in the sweep
+    // whose lines are rows, so those reads are coalesced.
     StageOut sy;
     sy.Un = nullptr;
     sy.Lprev = nullptr;
@@ -348,6 +388,12 @@ enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const doubl
     });
     HIP_TRY(hipGetLastError());
     return ENOMR_OK;
+}
+
+enomr_status launch_operator(enomr_ctx* ctx, const enomr_problem& p, const double* Us, StageOut so,
+                             uint8_t* idx, void* ws, const int* active)
+{
+    return launch_operator(ctx, p, Us, so, idx, alpha_bufs(p, ws), at<double>(ws, layout(p).L), active);
 }
 
 size_t idx_bytes(const enomr_problem& p)
@@ -565,10 +611,14 @@ enomr_status enomr_create(int device, void* hip_stream, enomr_ctx** out)
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_a), ta, sizeof(ta)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_wa), wa, sizeof(wa)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_candpool), cp, sizeof(cp)));
+    // this device's copy of the scratch array of enomr_rhs_noalloc
+    void* scratch_addr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&scratch_addr, HIP_SYMBOL(enomr::scratch)));
     enomr_ctx* c = new enomr_ctx;
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->status = nullptr;
+    c->scratch = static_cast<double*>(scratch_addr);
     hipError_t e = hipMalloc(&c->status, sizeof(unsigned));
     if (e != hipSuccess) {
         delete c;
@@ -648,6 +698,31 @@ enomr_status enomr_rhs(enomr_ctx* ctx, const enomr_problem* prob, const double* 
     so.dt = nullptr;
     so.stage = 0;
     return launch_operator(ctx, *prob, U, so, idx, ws, nullptr);
+}
+
+enomr_status enomr_rhs_noalloc(enomr_ctx* ctx, const enomr_problem* prob, const double* U, double* dUdt,
+                               uint8_t* idx)
+{
+    if (enomr_status st = check_ctx(ctx)) return st;
+    if (enomr_status st = check_problem(prob)) return st;
+    if (!U || !dUdt) return fail(ENOMR_EINVAL, "NULL array");
+    if (U == dUdt) return fail(ENOMR_EINVAL, "dUdt must not alias U");
+    if (!ctx->scratch) return fail(ENOMR_EHIP, "the scratch array has no device address");
+    const long need = doubles_needed(*prob);
+    if (need > (long)kScratchDoubles)
+        return fail(ENOMR_EINVAL, "enomr_rhs_noalloc: the problem's per-line alphas need " + std::to_string(need) +
+                                      " doubles of scratch; at most " + std::to_string(kScratchDoubles) +
+                                      " are available (use enomr_rhs with a workspace)");
+    const AlphaBufs ab = alpha_bufs_at(*prob, ctx->scratch);
+    if (enomr_status st = launch_alpha(ctx, *prob, U, ab, nullptr)) return st;
+    StageOut so;
+    so.Un = nullptr;
+    so.Lprev = nullptr;
+    so.out = dUdt;
+    so.dt = nullptr;
+    so.stage = 0;
+    // 2D: L_y goes through dUdt itself
+    return launch_operator(ctx, *prob, U, so, idx, ab, dUdt, nullptr);
 }
 
 enomr_status enomr_dt(enomr_ctx* ctx, const enomr_problem* prob, const double* U, double cfl, double* dt_dev,
