@@ -765,7 +765,7 @@ __device__ __forceinline__ double fallback_window(const Eig& e, const double (&A
 // faces c0 .. c0+TF-1 (cells c0 .. c0+TF-2).  DIR 0: lines are rows (x faces);
 // DIR 1: lines are columns (y faces), evaluated on the permuted state
 // (rho, n, m, E) so that the same x-normal formulas apply.  NCL >= TF+2R-1 is
-// the LDS stride per line.  VAR selects the operator variant (VAR_CHAR,
+// the number of cells per line the LDS holds.  VAR selects the operator variant (VAR_CHAR,
 // VAR_COMPONENT, VAR_FIELD).  All threads of the block must call it.
 template <int NV, int R, int DIR, int TF, int TL, int NCL, int VAR = VAR_CHAR>
 __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so, long line0, long c0,
@@ -854,8 +854,18 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     }
     __syncthreads();
 
-    const int tf = DIR == 0 ? threadIdx.x % TF : threadIdx.x / TL;
-    const int tl = DIR == 0 ? threadIdx.x / TF : threadIdx.x % TL;
+    // Which face a lane takes.  x faces: a wavefront covers FW consecutive
+    // faces of 64/FW neighbouring lines (a block rather than a strip of 64
+    // faces, so that fewer of its lanes sit idle while those whose windows
+    // straddle a discontinuity walk the candidate list), each group of FW
+    // lanes reading and writing one row's consecutive doubles.  y faces:
+    // lanes run across the TL lines first, the direction of contiguous memory.
+    constexpr int FW = TL >= 4 ? 16 : 64 / TL;   // x faces: faces per wavefront row
+    constexpr int LW = 64 / FW;                  // x faces: lines per wavefront
+    static_assert(DIR == 1 || (TL % LW == 0 && TF % FW == 0 && NT % 64 == 0), "x-face wavefront shape");
+    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+    const int tf = DIR == 0 ? (wv / (TL / LW)) * FW + ln % FW : threadIdx.x / TL;
+    const int tl = DIR == 0 ? (wv % (TL / LW)) * LW + ln / FW : threadIdx.x % TL;
     const long gl = line0 + tl;
     const long face = c0 + tf;
     const bool live = gl < nlines && face <= n;
@@ -1357,7 +1367,7 @@ constexpr int kB2NT = 256;
 template <int TF, int TL>
 struct B2Shape {
     static_assert(TF * TL == kB2NT, "four waves per workgroup");
-    static constexpr int NCL = TF + 17;   // LDS stride per line: the order-17 window
+    static constexpr int NCL = TF + 17;   // LDS cells per line: the order-17 window
     using Lds = SweepLds<4, NCL * TL, TF * TL>;
 };
 
