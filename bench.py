@@ -316,9 +316,10 @@ def run_batched(args):
 def run_batched_2d(args):
     """Batched 2D workload: 1024 independent 2D Euler problems (by default),
     nx, ny ~ U{32..128}, orders {7, 9, 13, 17}, seeded quadrants + vortices, x
-    periodic / y outflow, `batch2d_steps` SSP-RK3 steps in one graph launch of
-    the persistent 2D kernel, against per-problem launches of a sample of the
-    same problems."""
+    periodic / y outflow, `batch2d_steps` SSP-RK3 steps (one replay of the
+    batch's one-step graph per step: per stage and order, the alphas, the y
+    sweep and the x sweep over the tiles of all that order's problems),
+    against per-problem launches of a sample of the same problems."""
     import torch
 
     import paper_2311_15504_amd as enomr
@@ -366,7 +367,7 @@ def run_batched_2d(args):
     batch.close()
     ctx.close()
     return {"workload": "%d independent 2D Euler problems, nx, ny ~ U{32..%d}, orders {7,9,13,17}, seeded "
-                        "quadrants + vortices, %d SSP-RK3 steps at CFL 0.5, one graph launch"
+                        "quadrants + vortices, %d SSP-RK3 steps at CFL 0.5, one graph replay per step"
                         % (len(plist), args.batch2d_nmax, steps),
             "value": value, "unit": "cell-updates/s", "ms": ms, "total_cells": cells,
             "workgroups": info["workgroups"], "tile2d": list(info["tile2d"]),

@@ -250,13 +250,18 @@ enomr_status enomr_adjoint_steps(enomr_ctx *ctx, const enomr_problem *prob, int6
                                  void *ws);
 
 /*
- * Batched persistent execution: many independent 1D and 2D Euler problems
- * (uneven sizes and orders) advanced together by persistent launches replayed
- * from one hipGraph.  Each problem advances with its own per-stage alphas and
- * CFL time step exactly as enomr_advance() would advance it alone, and its
- * result is bitwise equal to that run.  A workgroup takes a whole problem
- * from a work queue (longest first) and runs all its steps; the 1D and the 2D
- * problems have a kernel each, the two running side by side in the graph.
+ * Batched execution: many independent 1D and 2D Euler problems (uneven
+ * sizes and orders) advanced together from captured hipGraphs.  Each problem
+ * advances with its own per-stage alphas and CFL time step exactly as
+ * enomr_advance() would advance it alone, and its result is bitwise equal to
+ * that run.  1D problems: one persistent launch for all steps, in which a
+ * workgroup takes a whole problem from a work queue (longest first) and runs
+ * all its steps.  2D problems: stage by stage, one launch per order for the
+ * alphas (and dt), one for the y faces and one for the x faces of all that
+ * order's problems (a tile per workgroup, largest problems first), the
+ * orders as parallel branches of a one-step graph replayed once per step.
+ * With both kinds, the 1D launch runs on a stream of its own beside the 2D
+ * steps.
  *
  * enomr_batch_create: probs[nprob] (ENOMR_EULER, ndim 1 or 2, any order
  * 5..17), U[nprob] device pointers to the problems' states ([3][nx] or
@@ -266,19 +271,19 @@ enomr_status enomr_adjoint_steps(enomr_ctx *ctx, const enomr_problem *prob, int6
  * problems on scratch copies for each tile width (64, 128, 256 faces) and
  * keeps the fastest; 0 uses 128; 64, 128 or 256 use that width; any other
  * value is ENOMR_EINVAL.  autotune = 1 also times one step of the 2D
- * problems for each tile shape of the 2D kernel (64 x 4, 32 x 8, 16 x 16
- * faces x lines) and keeps the fastest; otherwise the 2D kernel uses 32 x 8.
+ * problems for each tile shape of the 2D sweeps (64 x 4, 32 x 8, 16 x 16
+ * faces x lines) and keeps the fastest; otherwise the 2D sweeps use 32 x 8.
  * The tile shape does not change any result.
  * enomr_batch_advance: nsteps SSP-RK3 steps of every problem at CFL `cfl`.
- * enomr_batch_info: the 1D kernel's tile width, the workgroups of both
- * kernels, and the autotune times (ms, for widths 64/128/256; zeros without
- * autotune).  Any pointer may be NULL.
- * enomr_batch_info2d: the 2D kernel's tile shape and its autotune times (ms,
+ * enomr_batch_info: the 1D kernel's tile width, its workgroups plus those of
+ * the largest 2D sweep launch, and the autotune times (ms, for widths
+ * 64/128/256; zeros without autotune).  Any pointer may be NULL.
+ * enomr_batch_info2d: the 2D sweeps' tile shape and its autotune times (ms,
  * for 64 x 4, 32 x 8, 16 x 16; zeros without autotune).  Any pointer may be
  * NULL.
  * enomr_batch_set_tile2d: use the 2D tile shape tile_faces x tile_lines (one
  * of the three) from the next advance on; waits for the context's stream and
- * rebuilds the graph.  Other shapes: ENOMR_EINVAL.
+ * rebuilds the 2D step's graph.  Other shapes: ENOMR_EINVAL.
  */
 typedef struct enomr_batch enomr_batch;
 enomr_status enomr_batch_create(enomr_ctx *ctx, int32_t nprob, const enomr_problem *probs, double *const *U,

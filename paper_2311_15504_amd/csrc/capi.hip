@@ -49,21 +49,32 @@ struct enomr_batch {
     int nprob2 = 0;                // 2D problems
     int tf = 128;                  // faces per tile of the 1D kernel (autotuned)
     unsigned nblocks = 0;          // persistent workgroups of the 1D kernel
-    unsigned nblocks2 = 0;         // persistent workgroups of the 2D kernel
-    int shape2 = 1;                // the 2D kernel's tile shape: index into kB2Shapes (autotuned)
+    unsigned nblocks2 = 0;         // workgroups of the largest 2D sweep launch
+    int shape2 = 1;                // the 2D sweeps' tile shape: index into kB2Shapes (autotuned)
     double tune2_ms[3] = {0, 0, 0};// one-step times of the 2D tile shapes
     BatchProb* d_probs = nullptr;
     int* d_order = nullptr;
     BatchProb2* d_probs2 = nullptr;
-    int* d_order2 = nullptr;
-    int* d_queue = nullptr;        // [2]: the 1D and the 2D kernel's work counters
+    // 2D problems by order: group g holds d_list2[first .. first+count-1]
+    // (longest first), and its sweep launches take the tile lists at
+    // d_tiles2 + off[shape][dir] (tiles[shape][dir] entries; dir 0: x faces)
+    struct Group2 {
+        int R = 0, first = 0, count = 0;
+        long off[3][2] = {}, tiles[3][2] = {};
+    };
+    std::vector<Group2> groups2;
+    int* d_list2 = nullptr;
+    int2* d_tiles2 = nullptr;
+    int* d_queue = nullptr;        // [2]: work counters (the 1D kernel takes [0])
     BatchParams* d_params = nullptr;
     double* d_ws = nullptr;        // stage states (and 2D line buffers) of every problem
-    hipStream_t cap = nullptr;     // capture stream
-    hipStream_t cap2 = nullptr;    // second capture stream (2D kernel beside the 1D one)
-    hipEvent_t fork = nullptr, join = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;     // capture stream of the 1D launch; it runs there beside the 2D steps
+    hipStream_t cap2 = nullptr;    // capture stream of the 2D step
+    std::vector<hipStream_t> br;   // the 2D step's branches, one per order
+    std::vector<hipEvent_t> brev;
+    hipEvent_t fork = nullptr, join = nullptr, fork2 = nullptr;
+    hipGraph_t graph = nullptr, graph2 = nullptr;
+    hipGraphExec_t exec = nullptr, exec2 = nullptr;
     double tune_ms[3] = {0, 0, 0}; // one-step times of the tile widths 64, 128, 256
 };
 
@@ -1005,27 +1016,30 @@ constexpr int kB2Shapes[3][2] = {{64, 4}, {32, 8}, {16, 16}};
     default: { constexpr int TF = 32, TL = 8; __VA_ARGS__; } break;             \
     }
 
-hipError_t launch_batch2(const enomr_batch* b, int shape, unsigned nblocks, const BatchProb2* probs,
-                         hipStream_t st)
+// One SSP-RK3 step of one order's 2D problems on stream st: per stage the
+// alphas (and at the first stage dt), the y sweep, the x sweep.
+hipError_t launch_b2_group(const enomr_batch* b, int shape, const enomr_batch::Group2& g, const BatchProb2* probs,
+                           hipStream_t st)
 {
-    DISPATCH_SHAPE2(shape, hipLaunchKernelGGL((k_batch_euler2d<TF, TL>), dim3(nblocks), dim3(kB2NT), 0, st, probs,
-                                              b->d_order2, b->nprob2, b->d_queue + 1, b->d_params,
-                                              b->ctx->status));
+    const int2* tx = b->d_tiles2 + g.off[shape][0];
+    const int2* ty = b->d_tiles2 + g.off[shape][1];
+    const unsigned nx = (unsigned)g.tiles[shape][0], ny = (unsigned)g.tiles[shape][1];
+    unsigned* status = b->ctx->status;
+    for (int stage = 1; stage <= 3; ++stage) {
+        hipLaunchKernelGGL(k_batch2_alpha, dim3(g.count), dim3(kB2AlphaNT), 0, st, probs, b->d_list2 + g.first, stage,
+                           b->d_params, status);
+        DISPATCH_SHAPE2(shape, DISPATCH_R(2 * g.R - 1,
+            hipLaunchKernelGGL((k_batch2_sweep<R, 1, TF, TL>), dim3(ny), dim3(TF * TL), 0, st, probs, ty, stage, status);
+            hipLaunchKernelGGL((k_batch2_sweep<R, 0, TF, TL>), dim3(nx), dim3(TF * TL), 0, st, probs, tx, stage, status)));
+    }
     return hipGetLastError();
 }
 
-unsigned batch_blocks2(int shape, int nprob)
+long b2_tiles(int shape, int dir, long nx, long ny)
 {
-    int per_cu = 0, ncu = 0, dev = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    hipError_t e = hipErrorInvalidValue;
-    DISPATCH_SHAPE2(shape, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_euler2d<TF, TL>, kB2NT, 0));
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    if (ncu < 1) ncu = 1;
-    long nb = (long)per_cu * ncu;
-    if (nb > nprob) nb = nprob;
-    return (unsigned)(nb < 1 ? 1 : nb);
+    long t = 0;
+    DISPATCH_SHAPE2(shape, t = dir == 0 ? batch2_tiles<0, TF, TL>(nx, ny) : batch2_tiles<1, TF, TL>(nx, ny));
+    return t;
 }
 
 unsigned batch_blocks(int tf, int nprob)
@@ -1049,13 +1063,19 @@ void batch_free(enomr_batch* b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->exec2) (void)hipGraphExecDestroy(b->exec2);
+    if (b->graph2) (void)hipGraphDestroy(b->graph2);
     if (b->cap2) (void)hipStreamDestroy(b->cap2);
+    for (hipStream_t st : b->br) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : b->brev) (void)hipEventDestroy(ev);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->join) (void)hipEventDestroy(b->join);
+    if (b->fork2) (void)hipEventDestroy(b->fork2);
     (void)hipFree(b->d_probs);
     (void)hipFree(b->d_order);
     (void)hipFree(b->d_probs2);
-    (void)hipFree(b->d_order2);
+    (void)hipFree(b->d_list2);
+    (void)hipFree(b->d_tiles2);
     (void)hipFree(b->d_queue);
     (void)hipFree(b->d_params);
     (void)hipFree(b->d_ws);
@@ -1064,37 +1084,50 @@ void batch_free(enomr_batch* b)
 
 }  // namespace
 
-// Capture the persistent launches into a graph, replayed by every advance
-// (replacing a previous one).  With both kinds of problems the 2D kernel runs
-// beside the 1D one: the second stream forks from the capture stream before
-// either launch.  Streams of default priority.
+// Capture the 1D problems' persistent launch into a graph (all steps), and
+// one step of the 2D problems into another, one branch per order (streams of
+// default priority); advance replays the first once and the second once per
+// step.  Each replaces the previous one.
 enomr_status capture_batch(enomr_batch* b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
-    const int n1 = b->nprob, n2 = b->nprob2;
-    b->nblocks2 = n2 > 0 ? batch_blocks2(b->shape2, n2) : 0;
+    if (b->nprob == 0) return ENOMR_OK;
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(ENOMR_EHIP, "cannot begin capture");
-    hipError_t le = hipSuccess;
-    const bool both = n1 > 0 && n2 > 0;
-    hipStream_t s2 = both ? b->cap2 : b->cap;
-    if (both) {
-        if (le == hipSuccess) le = hipEventRecord(b->fork, b->cap);
-        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap2, b->fork, 0);
-    }
-    if (le == hipSuccess && n1 > 0) le = launch_batch(b, b->tf, b->d_probs, b->cap);
-    if (le == hipSuccess && n2 > 0) le = launch_batch2(b, b->shape2, b->nblocks2, b->d_probs2, s2);
-    if (both) {
-        if (le == hipSuccess) le = hipEventRecord(b->join, b->cap2);
-        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap, b->join, 0);
-    }
-    hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
+    const hipError_t le = launch_batch(b, b->tf, b->d_probs, b->cap);
+    const hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
     if (le != hipSuccess || ce != hipSuccess) return fail(ENOMR_EHIP, "capture of the batch launch failed");
     if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
         return fail(ENOMR_EHIP, "cannot instantiate the batch graph");
+    return ENOMR_OK;
+}
+
+enomr_status capture_batch2(enomr_batch* b)
+{
+    if (b->exec2) (void)hipGraphExecDestroy(b->exec2);
+    if (b->graph2) (void)hipGraphDestroy(b->graph2);
+    b->exec2 = nullptr;
+    b->graph2 = nullptr;
+    if (b->nprob2 == 0) return ENOMR_OK;
+    b->nblocks2 = 0;
+    for (const auto& g : b->groups2)
+        for (int d = 0; d < 2; ++d) b->nblocks2 = std::max(b->nblocks2, (unsigned)g.tiles[b->shape2][d]);
+    if (hipStreamBeginCapture(b->cap2, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(ENOMR_EHIP, "cannot begin capture");
+    hipError_t le = hipEventRecord(b->fork2, b->cap2);
+    for (size_t k = 0; k < b->groups2.size() && le == hipSuccess; ++k) {
+        le = hipStreamWaitEvent(b->br[k], b->fork2, 0);
+        if (le == hipSuccess) le = launch_b2_group(b, b->shape2, b->groups2[k], b->d_probs2, b->br[k]);
+        if (le == hipSuccess) le = hipEventRecord(b->brev[k], b->br[k]);
+        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap2, b->brev[k], 0);
+    }
+    const hipError_t ce = hipStreamEndCapture(b->cap2, &b->graph2);
+    if (le != hipSuccess || ce != hipSuccess) return fail(ENOMR_EHIP, "capture of the 2D batch step failed");
+    if (hipGraphInstantiate(&b->exec2, b->graph2, nullptr, nullptr, 0) != hipSuccess)
+        return fail(ENOMR_EHIP, "cannot instantiate the 2D batch graph");
     return ENOMR_OK;
 }
 
@@ -1122,7 +1155,7 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
             i2.push_back(i);
             const size_t plane = sizeof(double) * (size_t)p.nx * (size_t)p.ny;
             total += align_up(4 * plane) * 3 + align_up(sizeof(double) * (size_t)p.ny) +
-                     align_up(sizeof(double) * (size_t)p.nx);
+                     align_up(sizeof(double) * (size_t)p.nx) + align_up(sizeof(double));
         }
     }
     enomr_batch* b = new enomr_batch;
@@ -1168,6 +1201,7 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
         q.L = take(4 * plane);
         q.ax = take(sizeof(double) * (size_t)p.ny);
         q.ay = take(sizeof(double) * (size_t)p.nx);
+        q.dt = take(sizeof(double));
         q.nx = p.nx;
         q.ny = p.ny;
         q.ihx = 1.0 / p.hx;
@@ -1186,6 +1220,30 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
         return o;
     };
     const std::vector<int> order = lpt(cost), order2 = lpt(cost2);
+    // 2D problems by order (ascending), longest first within an order; the
+    // tile lists of each order, shape and direction follow its problems
+    std::vector<int> list2;
+    std::vector<int2> tiles2;
+    for (int R = 3; R <= 9; ++R) {
+        enomr_batch::Group2 g;
+        g.R = R;
+        g.first = (int)list2.size();
+        for (int k : order2)
+            if (hp2[k].R == R) list2.push_back(k);
+        g.count = (int)list2.size() - g.first;
+        if (g.count == 0) continue;
+        b->groups2.push_back(g);
+    }
+    for (int t = 0; t < 3; ++t)
+        for (auto& g : b->groups2)
+            for (int d = 0; d < 2; ++d) {
+                g.off[t][d] = (long)tiles2.size();
+                for (int i = g.first; i < g.first + g.count; ++i) {
+                    const long nt = b2_tiles(t, d, hp2[list2[i]].nx, hp2[list2[i]].ny);
+                    for (long j = 0; j < nt; ++j) tiles2.push_back(make_int2(list2[i], (int)j));
+                }
+                g.tiles[t][d] = (long)tiles2.size() - g.off[t][d];
+            }
     if (hipMalloc(&b->d_queue, sizeof(int) * 2) != hipSuccess || hipMalloc(&b->d_params, sizeof(BatchParams)) != hipSuccess)
         return bail(ENOMR_ENOMEM, "cannot allocate batch descriptors");
     if (b->nprob > 0) {
@@ -1198,10 +1256,12 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
     }
     if (b->nprob2 > 0) {
         if (hipMalloc(&b->d_probs2, sizeof(BatchProb2) * b->nprob2) != hipSuccess ||
-            hipMalloc(&b->d_order2, sizeof(int) * b->nprob2) != hipSuccess)
+            hipMalloc(&b->d_list2, sizeof(int) * list2.size()) != hipSuccess ||
+            hipMalloc(&b->d_tiles2, sizeof(int2) * tiles2.size()) != hipSuccess)
             return bail(ENOMR_ENOMEM, "cannot allocate batch descriptors");
         if (hipMemcpy(b->d_probs2, hp2.data(), sizeof(BatchProb2) * b->nprob2, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(b->d_order2, order2.data(), sizeof(int) * b->nprob2, hipMemcpyHostToDevice) != hipSuccess)
+            hipMemcpy(b->d_list2, list2.data(), sizeof(int) * list2.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b->d_tiles2, tiles2.data(), sizeof(int2) * tiles2.size(), hipMemcpyHostToDevice) != hipSuccess)
             return bail(ENOMR_EHIP, "cannot upload batch descriptors");
     }
 
@@ -1256,8 +1316,9 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
     }
     if (n1 > 0) b->nblocks = batch_blocks(b->tf, n1);
 
-    // Autotune the 2D kernel's tile shape the same way: one step of the 2D
-    // problems on scratch copies of their states, per shape.
+    // Autotune the 2D sweeps' tile shape the same way: one step of the 2D
+    // problems on scratch copies of their states, per shape (the orders one
+    // after another on the context's stream).
     const int n2 = b->nprob2;
     b->shape2 = 1;
     if (autotune == 1 && n2 > 0) {
@@ -1287,7 +1348,7 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
                                     hipMemcpyDeviceToDevice, ctx->stream) == hipSuccess;
             hipLaunchKernelGGL(k_set_batch_params, dim3(1), dim3(64), 0, ctx->stream, b->d_params, 0.5, 1L, b->d_queue);
             ok = ok && hipEventRecord(e0, ctx->stream) == hipSuccess;
-            ok = ok && launch_batch2(b, t, batch_blocks2(t, n2), d_tune, ctx->stream) == hipSuccess;
+            for (const auto& g : b->groups2) ok = ok && launch_b2_group(b, t, g, d_tune, ctx->stream) == hipSuccess;
             ok = ok && hipEventRecord(e1, ctx->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
             float ms = 0.0f;
             ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
@@ -1304,12 +1365,25 @@ enomr_status enomr_batch_create(enomr_ctx* ctx, int32_t nprob, const enomr_probl
         if (!ok) return bail(ENOMR_EHIP, "autotune failed");
     }
 
-    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&b->cap2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)
-        return bail(ENOMR_EHIP, "cannot create capture streams");
+    bool sok = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess &&
+               hipStreamCreateWithFlags(&b->cap2, hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&b->join, hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&b->fork2, hipEventDisableTiming) == hipSuccess;
+    for (size_t k = 0; sok && k < b->groups2.size(); ++k) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        sok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (sok) b->br.push_back(st);
+        sok = sok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (sok) b->brev.push_back(ev);
+    }
+    if (!sok) return bail(ENOMR_EHIP, "cannot create capture streams");
     if (enomr_status st = capture_batch(b)) {
+        batch_free(b);
+        return st;
+    }
+    if (enomr_status st = capture_batch2(b)) {
         batch_free(b);
         return st;
     }
@@ -1328,7 +1402,7 @@ enomr_status enomr_batch_set_tile2d(enomr_batch* b, int32_t tile_faces, int32_t 
     // let replays of the current graph finish before it is replaced
     HIP_TRY(hipStreamSynchronize(b->ctx->stream));
     b->shape2 = shape;
-    return capture_batch(b);
+    return capture_batch2(b);
 }
 
 enomr_status enomr_batch_advance(enomr_batch* b, double cfl, int64_t nsteps)
@@ -1336,10 +1410,22 @@ enomr_status enomr_batch_advance(enomr_batch* b, double cfl, int64_t nsteps)
     if (!b) return fail(ENOMR_EINVAL, "batch is NULL");
     if (enomr_status st = check_ctx(b->ctx)) return st;
     if (!(cfl > 0.0) || nsteps < 0) return fail(ENOMR_EINVAL, "bad cfl or nsteps");
-    hipLaunchKernelGGL(k_set_batch_params, dim3(1), dim3(64), 0, b->ctx->stream, b->d_params, cfl, (long)nsteps,
-                       b->d_queue);
+    hipStream_t st = b->ctx->stream;
+    hipLaunchKernelGGL(k_set_batch_params, dim3(1), dim3(64), 0, st, b->d_params, cfl, (long)nsteps, b->d_queue);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipGraphLaunch(b->exec, b->ctx->stream));
+    // the 1D launch (all steps) runs on its own stream beside the 2D steps
+    const bool both = b->exec && b->exec2;
+    if (both) {
+        HIP_TRY(hipEventRecord(b->fork, st));
+        HIP_TRY(hipStreamWaitEvent(b->cap, b->fork, 0));
+        HIP_TRY(hipGraphLaunch(b->exec, b->cap));
+        HIP_TRY(hipEventRecord(b->join, b->cap));
+    } else if (b->exec) {
+        HIP_TRY(hipGraphLaunch(b->exec, st));
+    }
+    if (b->exec2)
+        for (int64_t k = 0; k < nsteps; ++k) HIP_TRY(hipGraphLaunch(b->exec2, st));
+    if (both) HIP_TRY(hipStreamWaitEvent(st, b->join, 0));
     return ENOMR_OK;
 }
 

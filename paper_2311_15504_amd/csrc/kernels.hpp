@@ -1295,11 +1295,14 @@ __global__ __launch_bounds__(TF, 4) void k_batch_euler1d(const BatchProb* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Batched 2D Euler problems: one 256-thread workgroup advances a whole
-// problem, each stage as per-line alphas (a wave per row, then per column),
-// dt at the first stage, the y sweep into L_y and the x sweep with the RK
-// combination, over the same 64 x 4 tiles as the single-problem kernels, so
-// every problem's result equals its single-problem run bit for bit.
+// Batched 2D Euler problems, stage by stage: per stage, one workgroup per
+// problem takes its per-line alphas (a wave per row, then per column) and at
+// the first stage its dt; then one launch sweeps the y faces of every problem
+// of one order and one the x faces (with the RK combination), over a list of
+// tiles of all those problems.  The sweeps run the same tile code as the
+// single-problem kernels, so every problem's result equals its single-problem
+// run bit for bit, and each order has kernels of its own, so that each is
+// allocated the registers of its own window.
 // ---------------------------------------------------------------------------
 
 struct BatchProb2 {
@@ -1309,6 +1312,7 @@ struct BatchProb2 {
     double* L;       // L_y (workspace)
     double* ax;      // [ny] alphas of the rows
     double* ay;      // [nx] alphas of the columns
+    double* dt;      // the problem's time step (workspace)
     long nx, ny;
     double ihx, ihy;
     double gamma;
@@ -1316,164 +1320,179 @@ struct BatchProb2 {
     int bcx, bcy;
 };
 
-// Per-line |u|+c (rows, into ax) and |v|+c (columns, into ay), each line's
-// maximum taken by one wave; the same speed formula as k_alpha_euler.
+// Per-line |u|+c (rows, into ax) and |v|+c (columns, into ay) of one problem
+// by the NW waves of a workgroup, the speed formula of k_alpha_euler.  The
+// columns go in chunks of 64 (a lane per column, so that every load is a
+// row's consecutive doubles); wave w takes rows w, w+NW, ... of a chunk, KR of
+// them in flight at once, folding each row's maximum into ax[y] (a row
+// belongs to one wave) and keeping its columns' running maxima, which the
+// waves then combine through LDS (col: NW x 64 doubles).
+template <int NW, int KR>
 __device__ __forceinline__ void block_line_speeds_2d(const double* __restrict__ U, long nx, long ny, double gamma,
-                                                     unsigned* status, double* ax, double* ay)
+                                                     unsigned* status, double* ax, double* ay, double* col)
 {
     const long plane = nx * ny;
     const double gm1 = gamma - 1.0;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    auto speeds = [&](long g, bool flag, double& sx, double& sy) {
-        const double rho = U[g], m = U[plane + g], nn = U[2 * plane + g], E = U[3 * plane + g];
-        const double ir = 1.0 / rho;
-        const double u = m * ir;
-        const double v = nn * ir;
-        const double ke = 0.5 * (m * u + nn * v);
-        const double p = gm1 * (E - ke);
-        if (flag && (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(m) || !isfinite(nn)))
-            flag_nonphysical(status);
-        const double c = sqrt((gamma * p) * ir);
-        sx = fabs(u) + c;
-        sy = fabs(v) + c;
-    };
-    for (long y = wave; y < ny; y += nw) {
-        double mx = 0.0;
-        for (long x = lane; x < nx; x += 64) {
-            double sx, sy;
-            speeds(y * nx + x, true, sx, sy);
-            mx = fmax(mx, sx);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (long c0 = 0; c0 < nx; c0 += 64) {
+        const long x = c0 + lane;
+        const bool xin = x < nx;
+        double cm = 0.0;
+        for (long y0 = wave; y0 < ny; y0 += (long)NW * KR) {
+            double q[KR][4];
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const long y = y0 + (long)k * NW;
+                if (xin && y < ny) {
+                    const long g = y * nx + x;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) q[k][v] = U[v * plane + g];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const long y = y0 + (long)k * NW;
+                if (y >= ny) break;   // uniform across the wave
+                double sx = 0.0;
+                if (xin) {
+                    const double rho = q[k][0], m = q[k][1], nn = q[k][2], E = q[k][3];
+                    const double ir = 1.0 / rho;
+                    const double u = m * ir;
+                    const double v = nn * ir;
+                    const double ke = 0.5 * (m * u + nn * v);
+                    const double p = gm1 * (E - ke);
+                    if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(m) || !isfinite(nn))
+                        flag_nonphysical(status);
+                    const double c = sqrt((gamma * p) * ir);
+                    sx = fabs(u) + c;
+                    cm = fmax(cm, fabs(v) + c);
+                }
+                const double r = wave_max(sx);
+                if (lane == 0) ax[y] = c0 == 0 ? r : fmax(ax[y], r);
+            }
         }
-        mx = wave_max(mx);
-        if (lane == 0) ax[y] = mx;
-    }
-    for (long x = wave; x < nx; x += nw) {
-        double my = 0.0;
-        for (long y = lane; y < ny; y += 64) {
-            double sx, sy;
-            speeds(y * nx + x, false, sx, sy);
-            my = fmax(my, sy);
+        col[wave * 64 + lane] = cm;
+        __syncthreads();
+        if (wave == 0 && xin) {
+            double m = col[lane];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) m = fmax(m, col[w * 64 + lane]);
+            ay[x] = m;
         }
-        my = wave_max(my);
-        if (lane == 0) ay[x] = my;
+        __syncthreads();
     }
 }
 
-// Tile shapes of the batched 2D kernel (faces per line x lines, 256 threads):
-// the batch's autotuner picks one.  Small problems leave lanes of long tiles
-// idle at the line ends; short tiles stage more halo per face.
-constexpr int kB2NT = 256;
+__device__ __forceinline__ const double* batch2_stage_in(const BatchProb2& P, int stage)
+{
+    return stage == 1 ? P.U : (stage == 2 ? P.U1 : P.U2);
+}
 
-template <int TF, int TL>
-struct B2Shape {
-    static_assert(TF * TL == kB2NT, "four waves per workgroup");
-    static constexpr int NCL = TF + 17;   // LDS cells per line: the order-17 window
-    using Lds = SweepLds<4, NCL * TL, TF * TL>;
+// Stage `stage` (1..3) of problems list[0 .. gridDim.x-1], one per workgroup
+// of kB2AlphaNT threads: the alphas of the stage input, and at the first stage
+// dt = cfl / (max ax / hx + max ay / hy), the expression the single-problem dt
+// kernel evaluates.
+constexpr int kB2AlphaNT = 512;
+
+__global__ __launch_bounds__(kB2AlphaNT) void k_batch2_alpha(const BatchProb2* __restrict__ probs,
+                                                             const int* __restrict__ list, int stage,
+                                                             const BatchParams* prm, unsigned* status)
+{
+    constexpr int NW = kB2AlphaNT / 64;
+    __shared__ double col[NW * 64];
+    const BatchProb2 P = probs[list[blockIdx.x]];
+    const long nx = P.nx, ny = P.ny;
+    block_line_speeds_2d<NW, 4>(batch2_stage_in(P, stage), nx, ny, P.gamma, status, P.ax, P.ay, col);
+    if (stage != 1) return;   // uniform across the workgroup
+    // the lines' alphas were written by other waves: the barrier that ended
+    // the last chunk orders them before these reads
+    double mx = 0.0, my = 0.0;
+    for (long i = threadIdx.x; i < ny; i += blockDim.x) mx = fmax(mx, P.ax[i]);
+    for (long i = threadIdx.x; i < nx; i += blockDim.x) my = fmax(my, P.ay[i]);
+    mx = wave_max(mx);
+    my = wave_max(my);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        col[wave] = mx;
+        col[NW + wave] = my;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mx = col[0];
+        my = col[NW];
+        for (int w = 1; w < NW; ++w) {
+            mx = fmax(mx, col[w]);
+            my = fmax(my, col[NW + w]);
+        }
+        *P.dt = prm->cfl / (mx * P.ihx + my * P.ihy);
+    }
+}
+
+// One tile per workgroup from tiles[] ({problem, tile}; tile numbered as the
+// single-problem sweep numbers its workgroups), all problems of order 2R-1.
+// DIR 1: L_y of the stage input into P.L; DIR 0: L_y plus the x part, RK
+// stage `stage` combined into the stage output.
+template <int R, int TF, int TL>
+struct B2Occupancy {
+    // workgroups (of four waves) per CU that the LDS allows, at most four
+    static constexpr int lds = (int)sizeof(SweepLds<4, (TF + 2 * R - 1) * TL, TF * TL>);
+    static constexpr int value = 163840 / lds >= 4 ? 4 : 163840 / lds;
 };
 
-template <int R, int TF, int TL>
-__device__ __forceinline__ void run_problem_2d(const BatchProb2& P, const BatchParams& prm, unsigned* status,
-                                               char* lds_raw, double* red, double* s_dt)
+template <int R, int DIR, int TF, int TL>
+__global__ __launch_bounds__(TF* TL, (B2Occupancy<R, TF, TL>::value)) void k_batch2_sweep(const BatchProb2* __restrict__ probs,
+                                                            const int2* __restrict__ tiles, int stage,
+                                                            unsigned* status)
 {
-    using Lds = typename B2Shape<TF, TL>::Lds;
-    constexpr int kB2TF = TF, kB2TL = TL, kB2NCL = B2Shape<TF, TL>::NCL;
-    Lds& sm = *reinterpret_cast<Lds*>(lds_raw);
+    constexpr int NCL = TF + 2 * R - 1;
+    __shared__ SweepLds<4, NCL * TL, TF * TL> lds;
+    const int2 td = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const BatchProb2& P = probs[td.x];
     const long nx = P.nx, ny = P.ny;
-    for (long step = 0; step < prm.nsteps; ++step) {
-        for (int stage = 1; stage <= 3; ++stage) {
-            const double* Us = stage == 1 ? P.U : (stage == 2 ? P.U1 : P.U2);
-            double* out = stage == 1 ? P.U1 : (stage == 2 ? P.U2 : P.U);
-            block_line_speeds_2d(Us, nx, ny, P.gamma, status, P.ax, P.ay);
-            __syncthreads();
-            if (stage == 1) {
-                double mx = 0.0, my = 0.0;
-                for (long i = threadIdx.x; i < ny; i += blockDim.x) mx = fmax(mx, P.ax[i]);
-                for (long i = threadIdx.x; i < nx; i += blockDim.x) my = fmax(my, P.ay[i]);
-                mx = wave_max(mx);
-                my = wave_max(my);
-                if ((threadIdx.x & 63) == 0) {
-                    red[threadIdx.x >> 6] = mx;
-                    red[4 + (threadIdx.x >> 6)] = my;
-                }
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-                    my = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
-                    *s_dt = prm.cfl / (mx * P.ihx + my * P.ihy);
-                }
-                __syncthreads();
-            }
-            SweepIn in;
-            in.Us = Us;
-            in.status = status;
-            in.idx = nullptr;
-            in.active = nullptr;
-            in.nx = nx;
-            in.ny = ny;
-            in.gamma = P.gamma;
-            in.grav = 0.0;
-            // y sweep: L_y into P.L
-            in.alpha = P.ay;
-            in.ih = P.ihy;
-            in.bc = P.bcy;
-            StageOut sy;
-            sy.Un = nullptr;
-            sy.Lprev = nullptr;
-            sy.out = P.L;
-            sy.dt = nullptr;
-            sy.stage = 0;
-            for (long l0 = 0; l0 < nx; l0 += kB2TL)
-                for (long c0 = 0; c0 < ny; c0 += kB2TF - 1)
-                    sweep_tile<4, R, 1, kB2TF, kB2TL, kB2NCL>(in, sy, l0, c0, sm);
-            __syncthreads();
-            // x sweep: adds L_x and combines the RK stage
-            in.alpha = P.ax;
-            in.ih = P.ihx;
-            in.bc = P.bcx;
-            StageOut sx;
-            sx.Un = P.U;
-            sx.Lprev = P.L;
-            sx.out = out;
-            sx.dt = s_dt;
-            sx.stage = stage;
-            for (long l0 = 0; l0 < ny; l0 += kB2TL)
-                for (long c0 = 0; c0 < nx; c0 += kB2TF - 1)
-                    sweep_tile<4, R, 0, kB2TF, kB2TL, kB2NCL>(in, sx, l0, c0, sm);
-            __syncthreads();
-        }
+    const long n = DIR == 0 ? nx : ny, nlines = DIR == 0 ? ny : nx;
+    const unsigned nft = (unsigned)((n + TF - 2) / (TF - 1)), nlt = (unsigned)((nlines + TL - 1) / TL);
+    const unsigned t = (unsigned)td.y;
+    const unsigned ft = DIR == 0 ? t % nft : t / nlt;
+    const unsigned lt = DIR == 0 ? t / nft : t % nlt;
+    SweepIn in;
+    in.Us = batch2_stage_in(P, stage);
+    in.status = status;
+    in.idx = nullptr;
+    in.active = nullptr;
+    in.nx = nx;
+    in.ny = ny;
+    in.gamma = P.gamma;
+    in.grav = 0.0;
+    StageOut so;
+    if (DIR == 1) {
+        in.alpha = P.ay;
+        in.ih = P.ihy;
+        in.bc = P.bcy;
+        so.Un = nullptr;
+        so.Lprev = nullptr;
+        so.out = P.L;
+        so.dt = nullptr;
+        so.stage = 0;
+    } else {
+        in.alpha = P.ax;
+        in.ih = P.ihx;
+        in.bc = P.bcx;
+        so.Un = P.U;
+        so.Lprev = P.L;
+        so.out = stage == 1 ? P.U1 : (stage == 2 ? P.U2 : P.U);
+        so.dt = P.dt;
+        so.stage = stage;
     }
+    sweep_tile<4, R, DIR, TF, TL, NCL>(in, so, (long)lt * TL, (long)ft * (TF - 1), lds);
 }
 
-// Two workgroups per CU: the kernel holds every order's sweeps behind one
-// switch, and at four per CU it spilled about 300 VGPRs to scratch (measured
-// 15% slower on the batched 2D workload).
-template <int TF, int TL>
-__global__ __launch_bounds__(kB2NT, 2) void k_batch_euler2d(const BatchProb2* __restrict__ probs,
-                                                            const int* __restrict__ order, int nprob, int* queue,
-                                                            const BatchParams* prm, unsigned* status)
+// The number of tiles of one sweep of an nx x ny problem (the host builds the
+// tile lists with it).
+template <int DIR, int TF, int TL>
+__host__ __device__ constexpr long batch2_tiles(long nx, long ny)
 {
-    __shared__ __align__(16) char lds_raw[sizeof(typename B2Shape<TF, TL>::Lds)];
-    __shared__ double red[8];
-    __shared__ double s_dt;
-    __shared__ int s_k;
-    const BatchParams P = *prm;
-    for (;;) {
-        if (threadIdx.x == 0) s_k = atomicAdd(queue, 1);
-        __syncthreads();
-        const int k = s_k;
-        __syncthreads();
-        if (k >= nprob) return;   // the whole workgroup leaves together
-        const BatchProb2 pr = probs[order[k]];
-        switch (pr.R) {
-        case 3: run_problem_2d<3, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 4: run_problem_2d<4, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 5: run_problem_2d<5, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 6: run_problem_2d<6, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 7: run_problem_2d<7, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
-        case 8: run_problem_2d<8, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
-        default: run_problem_2d<9, TF, TL>(pr, P, status, lds_raw, red, &s_dt); break;
-        }
-    }
+    const long n = DIR == 0 ? nx : ny, nlines = DIR == 0 ? ny : nx;
+    return ((n + TF - 2) / (TF - 1)) * ((nlines + TL - 1) / TL);
 }
 
 }  // namespace enomr
