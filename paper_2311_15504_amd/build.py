@@ -17,6 +17,53 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+# Host code under AddressSanitizer and UndefinedBehaviorSanitizer, for the CPU
+# tests of the library's host paths; the device code is built as usual (it is
+# never launched there) and the host compiler's sanitizer flags apply to the
+# host pass only.
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def build_sanitized(out_dir, verbose=False):
+    """libenomr_san.so in out_dir, rebuilt only when the sources or flags
+    changed (the device code takes a minute or two).  Load it into a process
+    that preloads the compiler's AddressSanitizer runtime."""
+    import glob
+    import hashlib
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*"))) + [os.path.join(HERE, "..", "include", "enomr.h")]
+    flags = ["-O1", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math"] + DEVICE + SANITIZE
+    h = hashlib.sha256(" ".join(flags).encode())
+    for f in srcs:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    os.makedirs(out_dir, exist_ok=True)
+    lib = os.path.join(out_dir, "libenomr_san.so")
+    stamp = lib + ".sha256"
+    if os.path.exists(lib) and os.path.exists(stamp) and open(stamp).read() == h.hexdigest():
+        return lib
+    objs = []
+    for src, lang in (("tables.cpp", ["-x", "hip"]), ("capi.hip", [])):
+        obj = os.path.join(out_dir, src.split(".")[0] + ".o")
+        cmd = [HIPCC] + lang + ["-c", os.path.join(CSRC, src), "-o", obj] + flags
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    link = [HIPCC, "-shared", "-o", lib + ".tmp"] + objs + DEVICE + ["-fPIC", "-shared-libsan"] + SANITIZE[:4]
+    subprocess.check_call(link)
+    os.replace(lib + ".tmp", lib)
+    with open(stamp, "w") as fh:
+        fh.write(h.hexdigest())
+    return lib
+
+
+def asan_runtime():
+    """The AddressSanitizer runtime of hipcc's host compiler (to preload)."""
+    out = subprocess.check_output([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
+    return out if os.path.isabs(out) and os.path.exists(out) else None
+
+
 def build(verbose=False):
     objs = []
     tmp = os.path.join(HERE, "_build")

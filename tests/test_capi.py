@@ -154,3 +154,46 @@ def test_operator_variant_switches_are_checked_without_a_gpu():
     prob.recon = 7
     with pytest.raises(enomr.EnomrError):
         enomr.workspace_size(prob)
+
+
+def test_entry_points_reject_null_arguments_without_a_gpu():
+    # Every entry point, given a NULL context (or batch, problem or output),
+    # returns an error status with a message and touches no device; the
+    # destroy calls accept NULL.  The sanitized build runs this too.
+    L = enomr.lib()
+    prob = enomr.Problem.euler2d(64, 64, 0.1, 0.1, 9)
+    pp = ctypes.byref(prob)
+    size = ctypes.c_size_t()
+    calls = {
+        "enomr_create": (0, None, None),
+        "enomr_set_stream": (None, None),
+        "enomr_coefficients": (8, None, None, None, None),     # even order; its outputs are nullable
+        "enomr_recon_faces": (None, 9, 1, 100, None, None, None),
+        "enomr_workspace_size": (None, ctypes.byref(size)),
+        "enomr_rhs": (None, pp, None, None, None, None),
+        "enomr_rhs_noalloc": (None, pp, None, None, None),
+        "enomr_dt": (None, pp, None, 0.5, None, None),
+        "enomr_ssprk3_step": (None, pp, None, None, None, None),
+        "enomr_advance": (None, pp, None, 0.5, 1, 0.0, None, None),
+        "enomr_check": (None,),
+        "enomr_profile_start": (None,),
+        "enomr_profile_stop": (None, None, None),
+        "enomr_lssp_workspace_size": (None, 3, ctypes.byref(size)),
+        "enomr_lssp_advance": (None, pp, None, 0.1, 1, 3, None),
+        "enomr_rhs_adjoint": (None, pp, None, None, None, None, None, None),
+        "enomr_record_steps": (None, pp, None, 0.5, 1, None, None, None, None, None),
+        "enomr_adjoint_steps": (None, pp, 1, None, None, None, None, None, None),
+        "enomr_batch_create": (None, 1, pp, None, 0, None),
+        "enomr_batch_advance": (None, 0.5, 1),
+        "enomr_batch_info": (None, None, None, None),
+        "enomr_batch_info2d": (None, None, None, None),
+        "enomr_batch_set_tile2d": (None, 64, 4),
+    }
+    assert set(calls) | {"enomr_destroy", "enomr_batch_destroy", "enomr_last_error"} == set(_declared_symbols())
+    for name, args in calls.items():
+        st = getattr(L, name)(*args)
+        assert st != 0, name
+        assert L.enomr_last_error(), name
+    assert L.enomr_coefficients(9, None, None, None, None) == 0
+    assert L.enomr_destroy(None) == 0
+    assert L.enomr_batch_destroy(None) == 0
