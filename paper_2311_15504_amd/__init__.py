@@ -319,8 +319,9 @@ class Context:
 
 
 class Batch:
-    """Many independent 1D and 2D Euler problems advanced by persistent
-    launches replayed from one graph (enomr_batch_*).  `states` are the
+    """Many independent 1D and 2D Euler problems advanced by graph-replayed
+    launches (enomr_batch_*): one persistent launch for the 1D problems, a
+    one-step graph per step for the 2D ones.  `states` are the
     problems' [3][n] or [4][ny][nx] float64 CUDA tensors; they stay bound to
     the batch and are advanced in place."""
 
@@ -363,7 +364,7 @@ class Batch:
                 "tile2d": (tf2.value, tl2.value), "tune2d_ms": list(ms2)}
 
     def set_tile2d(self, tile_faces, tile_lines):
-        """Use the 2D kernel's tile shape tile_faces x tile_lines (64x4, 32x8 or 16x16)."""
+        """Use the 2D sweeps' tile shape tile_faces x tile_lines (64x4, 32x8 or 16x16)."""
         self.ctx._sync_stream()
         _call("enomr_batch_set_tile2d", self.handle, int(tile_faces), int(tile_lines))
 

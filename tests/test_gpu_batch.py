@@ -1,5 +1,5 @@
-"""Batched persistent execution (one hipGraph-replayed launch for many 1D
-and 2D Euler problems of uneven sizes and orders): each problem equals its
+"""Batched execution (graph-replayed launches for many 1D and 2D Euler
+problems of uneven sizes and orders): each problem equals its
 single-problem run bit for bit, and the oracle's run that follows the
 single-problem run's stencil choices at the ties (tests/parity.py) to the
 final-time tolerance."""
@@ -173,7 +173,7 @@ def test_batch_matches_oracle(ctx):
 
 def test_batch_2d_matches_oracle_every_order_bc_and_tile_shape(ctx):
     # 2D problems of uneven sizes at every order 5..17 and every boundary
-    # combination, in one batch, for each tile shape of the 2D kernel: every
+    # combination, in one batch, for each tile shape of the 2D sweeps: every
     # final state within the final-time tolerance of the oracle's run (which
     # follows the logged single-problem run's choices at the ties).
     import torch
@@ -280,7 +280,7 @@ def test_batch_reports_a_problem_the_method_drives_non_physical(ctx):
 
 @pytest.mark.parametrize("shape", [(64, 4), (32, 8), (16, 16)])
 def test_batch_2d_every_tile_shape_equals_single_problem_runs(ctx, shape):
-    # The 2D kernel's tile shapes partition the faces differently; every face
+    # The 2D sweeps' tile shapes partition the faces differently; every face
     # is computed the same way, so each shape gives the single-problem result.
     import torch
     import paper_2311_15504_amd as enomr
