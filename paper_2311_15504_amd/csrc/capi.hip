@@ -18,6 +18,7 @@ namespace enomr {
 __constant__ double c_a[kPool][kMaxW];
 __constant__ double c_wa[2][kPool][kMaxW];
 __constant__ int c_candpool[10][kPool];
+__constant__ double c_wrow[10][kRowsMax];
 
 // Device memory of enomr_rhs_noalloc, the entry point that allocates nothing:
 // the per-line alphas of one operator evaluation.  Each device the library
@@ -622,6 +623,16 @@ enomr_status enomr_create(int device, void* hip_stream, enomr_ctx** out)
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_a), ta, sizeof(ta)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_wa), wa, sizeof(wa)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_candpool), cp, sizeof(cp)));
+    // the f^+ window rows of candidates 1 .. n_cands(R)-4, per order
+    static double wr[10][kRowsMax];
+    for (int R = 0; R < 10; ++R) {
+        for (int e = 0; e < kRowsMax; ++e) wr[R][e] = 0.0;
+        if (R < 3) continue;
+        const int W = 2 * R - 1;
+        for (int c = 1; c <= n_cands(R) - 4; ++c)
+            for (int i = 0; i < W; ++i) wr[R][(c - 1) * W + i] = wa[0][cp[R][c]][9 - R + i];
+    }
+    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_wrow), wr, sizeof(wr)));
     // this device's copy of the scratch array of enomr_rhs_noalloc
     void* scratch_addr = nullptr;
     HIP_TRY(hipGetSymbolAddress(&scratch_addr, HIP_SYMBOL(enomr::scratch)));

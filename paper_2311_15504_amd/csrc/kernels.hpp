@@ -723,25 +723,36 @@ __device__ __forceinline__ double char_value(const Eig& e, const double (&A)[NV]
     }
 }
 
+// Window-aligned a_l rows of the candidates beyond the full stencil, in list
+// order, for the f^+ window of each order: c_wrow[R][(c-1)(2R-1) + i]
+// multiplies window entry i for candidate c = 1 .. n_cands(R)-4 (zero outside
+// the stencil).  The f^- row of a candidate is the same row reversed.
+constexpr int kRowsMax = (kPool - 4) * kMaxW;
+extern __constant__ double c_wrow[10][kRowsMax];
+
 // LDS of one sweep tile: split fluxes and Roe inputs of NCELL staged cells
-// (structure of arrays) and the NFACE face fluxes.
+// (structure of arrays) and the NFACE face fluxes F[q * NFACE + face].  Until
+// the face fluxes are written, the F area holds the order's candidate rows
+// (c_wrow), which the fallback reads.
 template <int NV, int NCELL, int NFACE>
 struct SweepLds {
     double Gp[NV][NCELL];
     double Gm[NV][NCELL];
     double Sq[NCELL], Un[NCELL], H[NCELL];
     double Ut[NV == 4 ? NCELL : 1];
-    double F[NV][NFACE];
+    double F[NV * NFACE > kRowsMax ? NV * NFACE : kRowsMax];
 };
 
 // Steps 3.1/3.2 beyond the full stencil for field Q and sign S at one face:
 // project the sign's window (ascending cells, LDS entries lp0 + i*STEP),
 // build its difference table in place, and evaluate the chosen candidate's
 // flux chain on a second projection of the window (bitwise the same values;
-// re-projecting is cheaper than holding the window in registers).
+// re-projecting is cheaper than holding the window in registers).  rows: the
+// order's candidate rows in LDS (f^+ frame; f^- reads each row reversed).
 template <int NV, int R, int S, int Q, int STEP, int NCELL, int VAR>
 __device__ __forceinline__ double fallback_window(const Eig& e, const double (&A)[NV][NCELL],
-                                                  const double (&B)[NV][NCELL], double aq, int lp0, int& id)
+                                                  const double (&B)[NV][NCELL], double aq, int lp0,
+                                                  const double* rows, int& id)
 {
     constexpr int W = 2 * R - 1;
     auto proj = [&](int i) { return char_value<NV, VAR, S, Q, NCELL>(e, A, B, aq, lp0 + i * STEP); };
@@ -751,10 +762,10 @@ __device__ __forceinline__ double fallback_window(const Eig& e, const double (&A
     const double f0 = w[R - 1], lo = w[R - 2], hi = w[R];
     const int c = first_passing<R, S>(w, baseline_is<R, S>(w));
     if (c >= 0) {
-        const double* wa = &c_wa[S > 0 ? 0 : 1][c_candpool[R][c]][9 - R];
-        double f = wa[0] * proj(0);
+        const double* wa = rows + (c - 1) * W;
+        double f = wa[S > 0 ? 0 : W - 1] * proj(0);
 #pragma unroll
-        for (int i = 1; i < W; ++i) f = fma(wa[i], proj(i), f);
+        for (int i = 1; i < W; ++i) f = fma(wa[S > 0 ? i : W - 1 - i], proj(i), f);
         id = c;
         return f;
     }
@@ -793,7 +804,17 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     constexpr int NE = NCU * TL;
     constexpr int NIT = (NE + NT - 1) / NT;
     double Ust[NIT][NV];
+    // the candidate rows of the fallback, into the face-flux area (free until
+    // the fluxes are written)
+    constexpr int NROW = (n_cands(R) - 4) * W;
+    constexpr int NRIT = (NROW + NT - 1) / NT;
+    double rowv[NRIT];
     __builtin_amdgcn_s_setprio(2);   // issue this tile's loads ahead of other waves' arithmetic
+#pragma unroll
+    for (int it = 0; it < NRIT; ++it) {
+        const int e = threadIdx.x + it * NT;
+        if (e < NROW) rowv[it] = c_wrow[R][e];
+    }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int e = threadIdx.x + it * NT;
@@ -807,6 +828,11 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         }
     }
     __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+    for (int it = 0; it < NRIT; ++it) {
+        const int e = threadIdx.x + it * NT;
+        if (e < NROW) sm.F[e] = rowv[it];
+    }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int e = threadIdx.x + it * NT;
@@ -870,6 +896,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     const long face = c0 + tf;
     const bool live = gl < nlines && face <= n;
 
+    double Fh[NV];
     if (live) {
         const int jp = tf + R - 1;   // left cell of the face in the tile
         const int pl = lpos(tl, jp), pr = lpos(tl, jp + 1);
@@ -1045,21 +1072,21 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
                 const int lpp = lpos(tl, jp - (R - 1)), lpm = lpos(tl, jp - (R - 2));
                 constexpr int NC = NCL * TL;
                 switch (kk) {
-                case 0: res = fallback_window<NV, R, +1, 0, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[0], lpp, id); hp[0] = res; break;
-                case 1: res = fallback_window<NV, R, -1, 0, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[0], lpm, id); hm[0] = res; break;
-                case 2: res = fallback_window<NV, R, +1, 1, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[1], lpp, id); hp[1] = res; break;
-                case 3: res = fallback_window<NV, R, -1, 1, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[1], lpm, id); hm[1] = res; break;
-                case 4: res = fallback_window<NV, R, +1, 2, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[2], lpp, id); hp[2] = res; break;
-                case 5: res = fallback_window<NV, R, -1, 2, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[2], lpm, id); hm[2] = res; break;
+                case 0: res = fallback_window<NV, R, +1, 0, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[0], lpp, sm.F, id); hp[0] = res; break;
+                case 1: res = fallback_window<NV, R, -1, 0, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[0], lpm, sm.F, id); hm[0] = res; break;
+                case 2: res = fallback_window<NV, R, +1, 1, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[1], lpp, sm.F, id); hp[1] = res; break;
+                case 3: res = fallback_window<NV, R, -1, 1, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[1], lpm, sm.F, id); hm[1] = res; break;
+                case 4: res = fallback_window<NV, R, +1, 2, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[2], lpp, sm.F, id); hp[2] = res; break;
+                case 5: res = fallback_window<NV, R, -1, 2, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[2], lpm, sm.F, id); hm[2] = res; break;
                 case 6:
                     if constexpr (NV == 4) {
-                        res = fallback_window<NV, R, +1, 3, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[NV - 1], lpp, id);
+                        res = fallback_window<NV, R, +1, 3, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[NV - 1], lpp, sm.F, id);
                         hp[NV - 1] = res;
                     }
                     break;
                 default:
                     if constexpr (NV == 4) {
-                        res = fallback_window<NV, R, -1, 3, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[NV - 1], lpm, id);
+                        res = fallback_window<NV, R, -1, 3, LSTEP, NC, VAR>(e, sm.Gp, sm.Gm, af[NV - 1], lpm, sm.F, id);
                         hm[NV - 1] = res;
                     }
                     break;
@@ -1068,7 +1095,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             }
         }
 
-        double wh[NV], Fh[NV];
+        double wh[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) wh[q] = hp[q] + hm[q];
         if constexpr (VAR == VAR_COMPONENT) {
@@ -1077,8 +1104,6 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         } else {
             back_project<NV>(e, wh, Fh);
         }
-#pragma unroll
-        for (int q = 0; q < NV; ++q) sm.F[q][fpos(tl, tf)] = Fh[q];
 
         if (in.idx) {
             uint8_t* dst = DIR == 0 ? in.idx + ((gl * (n + 1) + face) * NV) * 2
@@ -1088,7 +1113,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         }
     }
     // ---- conservative difference and output; the cell's operands are
-    // requested before the barrier so that their latency overlaps it
+    // requested before the barriers so that their latency overlaps them
     const long cell = c0 + tf;
     const bool outc = gl < nlines && tf < TC && cell < n;
     const long g = outc ? gidx(gl, cell) : 0;
@@ -1110,13 +1135,18 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             s_rv = in.Us[2 * plane + g];
         }
     }
+    __syncthreads();   // every fallback is done with the candidate rows
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sm.F[q * NT + fpos(tl, tf)] = Fh[q];
+    }
     __syncthreads();
     if (outc) {
         const double dt = so.stage ? *so.dt : 0.0;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const int v = gvar(q);
-            double L = -((sm.F[q][fpos(tl, tf + 1)] - sm.F[q][fpos(tl, tf)]) * in.ih);
+            double L = -((sm.F[q * NT + fpos(tl, tf + 1)] - sm.F[q * NT + fpos(tl, tf)]) * in.ih);
             if (so.Lprev) L = lp[q] + L;
             if (SRC && in.grav != 0.0) {
                 if (v == 2) L = L + in.grav * s_rho;
@@ -1259,8 +1289,12 @@ __device__ __forceinline__ void run_problem(const BatchProb& P, const BatchParam
             so.out = out;
             so.dt = s_dt;
             so.stage = stage;
-            for (long c0 = 0; c0 < P.n; c0 += TF - 1) sweep_tile<3, R, 0, TF, 1, TF + 17>(in, so, 0, c0, sm);
-            __syncthreads();
+            // a tile's staging overwrites the face fluxes the previous tile's
+            // output reads
+            for (long c0 = 0; c0 < P.n; c0 += TF - 1) {
+                sweep_tile<3, R, 0, TF, 1, TF + 17>(in, so, 0, c0, sm);
+                __syncthreads();
+            }
         }
     }
 }
