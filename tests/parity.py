@@ -193,6 +193,9 @@ def follow_run_2d(ctx, prob, U0, nsteps, cfl=0.5, what="euler2d run", **kw):
             worst = max(worst, rep.max_abs_mu)
             us = oracle.ssprk3_combine(s + 1, un, us, L, dt_o)
         Uo = us
+        if prob.nx * prob.ny >= 1 << 20:
+            # a progress line per step of the large runs (minutes of oracle time)
+            print("%s step %d/%d: ties so far %d (max |mu| %.3g)" % (what, step + 1, nsteps, ties, worst), flush=True)
     got = host(U)
     errs = rel_err_per_var(got, Uo, floor=1.0)
     print("%s order %d %dx%d, %d steps: ties %d (max |mu| %.3g); final rel err %.3g"
