@@ -799,11 +799,12 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     auto gidx = [nx](long line, long cell) { return DIR == 0 ? line * nx + cell : cell * nx + line; };
 
     // ---- stage the tile: primitives, LF split G = (F +- alpha U)/2, Roe inputs.
-    // A thread stages up to NIT cells; all their loads are issued before any
-    // is used, so the staging costs one memory round trip, not NIT.
+    // A thread stages up to NIT cells; all their loads (the cells' line alpha
+    // included) are issued before any is used, so the staging costs one
+    // memory round trip, not NIT.
     constexpr int NE = NCU * TL;
     constexpr int NIT = (NE + NT - 1) / NT;
-    double Ust[NIT][NV];
+    double Ust[NIT][NV], alst[NIT];
     // the candidate rows of the fallback, into the face-flux area (free until
     // the fluxes are written)
     constexpr int NROW = (n_cands(R) - 4) * W;
@@ -825,6 +826,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             const long g = gidx(gl, map_cell(c0 - R + cell, n, in.bc));
 #pragma unroll
             for (int q = 0; q < NV; ++q) Ust[it][q] = in.Us[gvar(q) * plane + g];
+            if constexpr (VAR != VAR_FIELD) alst[it] = in.alpha[gl];
         }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -863,7 +865,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
                 sm.Gm[q][lp] = Uc[q];
             }
         } else {
-            const double al = in.alpha[gl];
+            const double al = alst[it];
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 const double t = al * Uc[q];
@@ -1122,7 +1124,9 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     // rho v of the cell
     constexpr bool SRC = NV == 4;
     double s_rho = 0.0, s_rv = 0.0;
+    double dt = 0.0;
     if (outc) {
+        if (so.stage) dt = *so.dt;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const long i = gvar(q) * plane + g;
@@ -1142,7 +1146,6 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     }
     __syncthreads();
     if (outc) {
-        const double dt = so.stage ? *so.dt : 0.0;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const int v = gvar(q);
