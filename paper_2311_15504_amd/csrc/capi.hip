@@ -160,7 +160,7 @@ int variant(const enomr_problem& p)
 // Workspace: two stage states, one operator buffer, per-line alphas and a
 // few device scalars.
 struct Layout {
-    size_t U1, U2, L, ax, ay, dt, t, active, adj_tmp, total;
+    size_t U1, U2, L, ax, ay, ax2, ay2, dt, t, active, adj_tmp, total;
 };
 
 Layout layout(const enomr_problem& p)
@@ -175,6 +175,9 @@ Layout layout(const enomr_problem& p)
     const size_t na = p.alpha_mode == ENOMR_ALPHA_FIELD ? 3 : 1;
     w.ax = off; off += align_up(sizeof(double) * na * (size_t)p.ny);
     w.ay = off; off += align_up(sizeof(double) * na * (size_t)(p.ndim == 2 ? p.nx : 1));
+    // a second set: the stages of a run alternate between the two
+    w.ax2 = off; off += align_up(sizeof(double) * na * (size_t)p.ny);
+    w.ay2 = off; off += align_up(sizeof(double) * na * (size_t)(p.ndim == 2 ? p.nx : 1));
     w.dt = off; off += 256;
     w.t = off; off += 256;
     w.active = off; off += 256;
@@ -265,6 +268,15 @@ AlphaBufs alpha_bufs(const enomr_problem& p, void* ws)
                      (long)(w.ay - w.ax) / (long)sizeof(double) + alpha_count_y(p)};
 }
 
+// Alpha set k % 2 of a run's stages (set 0 is the one alpha_bufs gives).
+AlphaBufs alpha_bufs_run(const enomr_problem& p, void* ws, long k)
+{
+    if (k % 2 == 0) return alpha_bufs(p, ws);
+    const Layout w = layout(p);
+    return AlphaBufs{at<double>(ws, w.ax2), at<double>(ws, w.ay2),
+                     (long)(w.ay2 - w.ax2) / (long)sizeof(double) + alpha_count_y(p)};
+}
+
 // The same two arrays packed from `base` (256-byte aligned), for
 // enomr_rhs_noalloc; doubles_needed() is their extent.
 long alpha_ax_extent(const enomr_problem& p) { return (alpha_count_x(p) + 31) & ~31L; }
@@ -274,30 +286,39 @@ AlphaBufs alpha_bufs_at(const enomr_problem& p, double* base)
     return AlphaBufs{base, base + alpha_ax_extent(p), doubles_needed(p)};
 }
 
-// Alphas of every line of `Us` into ab (zeroed first).
+// Alphas of every line of `Us` into ab (zeroed first).  With `next` (Euler
+// only), ab already holds zeros and the alpha kernel zeroes `next`, the
+// buffer of the run's following stage, instead of a fill launch.
 enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* Us, const AlphaBufs& ab,
-                          const int* active)
+                          const int* active, const AlphaBufs* next = nullptr)
 {
     double* ax = ab.ax;
     double* ay = ab.ay;
     const bool pf = p.alpha_mode == ENOMR_ALPHA_FIELD;
     timed(ctx, PROF_AUX, [&] {
         const long nfill = ab.nfill;
-        hipLaunchKernelGGL(k_fill, dim3(blocks_for(nfill, 256)), dim3(256), 0, ctx->stream, ax, nfill, 0.0);
+        double* zp = nullptr;
+        long zn = 0;
+        if (next && p.system == ENOMR_EULER) {
+            zp = next->ax;
+            zn = next->nfill;
+        } else {
+            hipLaunchKernelGGL(k_fill, dim3(blocks_for(nfill, 256)), dim3(256), 0, ctx->stream, ax, nfill, 0.0);
+        }
         if (p.system == ENOMR_EULER) {
             dim3 grid(blocks_for(p.nx, 64), blocks_for(p.ny, 32));
             if (pf && p.ndim == 2)
                 hipLaunchKernelGGL((k_alpha_euler<4, true>), grid, dim3(256), 0, ctx->stream, Us, (long)p.nx,
-                                   (long)p.ny, p.gamma, ax, ay, ctx->status, active);
+                                   (long)p.ny, p.gamma, ax, ay, ctx->status, active, zp, zn);
             else if (pf)
                 hipLaunchKernelGGL((k_alpha_euler<3, true>), grid, dim3(256), 0, ctx->stream, Us, (long)p.nx,
-                                   (long)p.ny, p.gamma, ax, ay, ctx->status, active);
+                                   (long)p.ny, p.gamma, ax, ay, ctx->status, active, zp, zn);
             else if (p.ndim == 2)
                 hipLaunchKernelGGL(k_alpha_euler<4>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
-                                   p.gamma, ax, ay, ctx->status, active);
+                                   p.gamma, ax, ay, ctx->status, active, zp, zn);
             else
                 hipLaunchKernelGGL(k_alpha_euler<3>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
-                                   p.gamma, ax, ay, ctx->status, active);
+                                   p.gamma, ax, ay, ctx->status, active, zp, zn);
         } else {
             const unsigned nb = blocks_for(p.nx, 256) < 64 ? blocks_for(p.nx, 256) : 64;
             hipLaunchKernelGGL(k_alpha_scalar, dim3(nb), dim3(256), 0, ctx->stream, Us, (long)p.nx,
@@ -415,8 +436,8 @@ size_t idx_bytes(const enomr_problem& p)
     return (size_t)p.ny * (p.nx + 1) * 8 + (size_t)(p.ny + 1) * p.nx * 8;
 }
 
-enomr_status launch_dt(enomr_ctx* ctx, const enomr_problem& p, double cfl, void* ws, double* dt, double t_end,
-                       double* dt_log, long step)
+enomr_status launch_dt(enomr_ctx* ctx, const enomr_problem& p, double cfl, void* ws, const AlphaBufs& ab,
+                       double* dt, double t_end, double* dt_log, long step)
 {
     const Layout w = layout(p);
     // per-field alphas: the maximum over the three planes is max(|u|+c)
@@ -424,17 +445,21 @@ enomr_status launch_dt(enomr_ctx* ctx, const enomr_problem& p, double cfl, void*
     const long nax = p.system == ENOMR_EULER ? na * p.ny : 1;
     const long nay = p.ndim == 2 ? na * p.nx : 0;
     timed(ctx, PROF_AUX, [&] {
-        hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, at<double>(ws, w.ax), nax,
-                           at<double>(ws, w.ay), nay, cfl, 1.0 / p.hx, p.ndim == 2 ? 1.0 / p.hy : 0.0, t_end, dt,
-                           at<double>(ws, w.t), at<int>(ws, w.active), dt_log, step);
+        hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, ab.ax, nax, ab.ay, nay, cfl, 1.0 / p.hx,
+                           p.ndim == 2 ? 1.0 / p.hy : 0.0, t_end, dt, at<double>(ws, w.t), at<int>(ws, w.active),
+                           dt_log, step);
     });
     HIP_TRY(hipGetLastError());
     return ENOMR_OK;
 }
 
-// One SSP-RK3 step of U in place.
+// One SSP-RK3 step of U in place.  With run (the count of the run's stages
+// so far), stage k takes alpha set k % 2, whose zeros the previous stage's
+// alpha launch wrote, and its own alpha launch zeroes the other set;
+// alpha_ready: the first stage's alphas (and dt) are already in place.
+// Without run, every stage fills set 0 before its alpha launch.
 enomr_status rk3_step(enomr_ctx* ctx, const enomr_problem& p, double* U, const double* dt, void* ws,
-                      uint8_t* idx_log, const int* active, bool alpha_ready)
+                      uint8_t* idx_log, const int* active, bool alpha_ready, long* run = nullptr)
 {
     const Layout w = layout(p);
     double* U1 = at<double>(ws, w.U1);
@@ -443,8 +468,10 @@ enomr_status rk3_step(enomr_ctx* ctx, const enomr_problem& p, double* U, const d
     double* stage_out[3] = {U1, U2, U};
     const size_t ib = idx_bytes(p);
     for (int s = 0; s < 3; ++s) {
+        const AlphaBufs ab = run ? alpha_bufs_run(p, ws, *run) : alpha_bufs(p, ws);
         if (!(s == 0 && alpha_ready)) {
-            enomr_status st = launch_alpha(ctx, p, stage_in[s], ws, active);
+            const AlphaBufs next = alpha_bufs_run(p, ws, run ? *run + 1 : 1);
+            enomr_status st = launch_alpha(ctx, p, stage_in[s], ab, active, run ? &next : nullptr);
             if (st) return st;
         }
         StageOut so;
@@ -453,8 +480,10 @@ enomr_status rk3_step(enomr_ctx* ctx, const enomr_problem& p, double* U, const d
         so.out = stage_out[s];
         so.dt = dt;
         so.stage = s + 1;
-        enomr_status st = launch_operator(ctx, p, stage_in[s], so, idx_log ? idx_log + s * ib : nullptr, ws, active);
+        enomr_status st = launch_operator(ctx, p, stage_in[s], so, idx_log ? idx_log + s * ib : nullptr, ab,
+                                          at<double>(ws, w.L), active);
         if (st) return st;
+        if (run) ++*run;
     }
     return ENOMR_OK;
 }
@@ -495,7 +524,7 @@ enomr_status record_steps(enomr_ctx* ctx, const enomr_problem& p, double* U, dou
             hipLaunchKernelGGL(k_copy1, dim3(1), dim3(64), 0, ctx->stream, al + s, at<double>(ws, w.ax));
             HIP_TRY(hipGetLastError());
             if (s == 0)
-                if (enomr_status st = launch_dt(ctx, p, cfl, ws, dt, 0.0, nullptr, 0)) return st;
+                if (enomr_status st = launch_dt(ctx, p, cfl, ws, alpha_bufs(p, ws), dt, 0.0, nullptr, 0)) return st;
             StageOut so;
             so.Un = S[0];
             so.Lprev = nullptr;
@@ -755,7 +784,7 @@ enomr_status enomr_dt(enomr_ctx* ctx, const enomr_problem* prob, const double* U
     if (!U || !dt_dev || !ws) return fail(ENOMR_EINVAL, "NULL array");
     if (!(cfl > 0.0)) return fail(ENOMR_EINVAL, "cfl must be > 0");
     if (enomr_status st = launch_alpha(ctx, *prob, U, ws, nullptr)) return st;
-    return launch_dt(ctx, *prob, cfl, ws, dt_dev, 0.0, nullptr, 0);
+    return launch_dt(ctx, *prob, cfl, ws, alpha_bufs(*prob, ws), dt_dev, 0.0, nullptr, 0);
 }
 
 enomr_status enomr_ssprk3_step(enomr_ctx* ctx, const enomr_problem* prob, double* U, const double* dt_dev,
@@ -783,10 +812,21 @@ enomr_status enomr_advance(enomr_ctx* ctx, const enomr_problem* prob, double* U,
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, ctx->stream, active, 1);
     HIP_TRY(hipGetLastError());
     const int* act = t_end > 0.0 ? active : nullptr;
+    // the stages alternate between the two alpha sets: each stage's alpha
+    // launch zeroes the next stage's set, so only the first needs a fill
+    long run = 0;
+    const bool euler = prob->system == ENOMR_EULER;
+    if (euler && nsteps > 0) {
+        const AlphaBufs a0 = alpha_bufs_run(*prob, ws, 0);
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(a0.nfill, 256)), dim3(256), 0, ctx->stream, a0.ax, a0.nfill, 0.0);
+        HIP_TRY(hipGetLastError());
+    }
     for (int64_t s = 0; s < nsteps; ++s) {
-        if (enomr_status st = launch_alpha(ctx, *prob, U, ws, act)) return st;
-        if (enomr_status st = launch_dt(ctx, *prob, cfl, ws, dt, t_end, dt_log, (long)s)) return st;
-        if (enomr_status st = rk3_step(ctx, *prob, U, dt, ws, nullptr, act, true)) return st;
+        const AlphaBufs ab = alpha_bufs_run(*prob, ws, run);
+        const AlphaBufs next = alpha_bufs_run(*prob, ws, run + 1);
+        if (enomr_status st = launch_alpha(ctx, *prob, U, ab, act, euler ? &next : nullptr)) return st;
+        if (enomr_status st = launch_dt(ctx, *prob, cfl, ws, ab, dt, t_end, dt_log, (long)s)) return st;
+        if (enomr_status st = rk3_step(ctx, *prob, U, dt, ws, nullptr, act, true, euler ? &run : nullptr)) return st;
     }
     return ENOMR_OK;
 }

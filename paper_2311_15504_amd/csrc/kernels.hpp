@@ -86,12 +86,20 @@ __global__ void k_alpha_scalar(const double* __restrict__ u, long n, int flux, d
 // nv = 3: alpha_x[0] = max(|u|+c).  Tile: 64 columns x (4*8) rows per block.
 // PF (per-field alphas): three planes per direction, alpha_x[k * ny + y] =
 // max_x of |u-c|, |u|, |u+c| for k = 0, 1, 2 (alpha_y likewise with v).
+// ax and ay must hold zeros.  The kernel also zeroes zp[0 .. zn-1] (a run's
+// other alpha buffer, for the next stage; zn = 0: none), which saves that
+// stage a fill launch.
 template <int NV, bool PF = false>
 __global__ __launch_bounds__(256) void k_alpha_euler(const double* __restrict__ U, long nx, long ny,
                                                       double gamma, double* ax, double* ay,
-                                                      unsigned* status, const int* active)
+                                                      unsigned* status, const int* active, double* zp, long zn)
 {
     if (active && *active == 0) return;
+    {
+        const long nth = (long)gridDim.x * gridDim.y * blockDim.x;
+        for (long i = ((long)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; i < zn; i += nth)
+            zp[i] = 0.0;
+    }
     if constexpr (PF) {
         __shared__ double colf[3][4][64];
         const long plane = nx * ny;
