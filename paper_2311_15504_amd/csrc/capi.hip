@@ -509,9 +509,15 @@ enomr_status launch_adjoint_stage(enomr_ctx* ctx, const enomr_problem& p, AdjIn 
 enomr_status record_steps(enomr_ctx* ctx, const enomr_problem& p, double* U, double cfl, int64_t nsteps,
                           double* stages, uint8_t* idx_log, double* alpha_log, double* dt_log, void* ws)
 {
-    const Layout w = layout(p);
     const size_t ns = (size_t)3 * p.nx;
     const size_t ib = idx_bytes(p);
+    // alternating alpha sets, as in enomr_advance: one fill for the run
+    long run = 0;
+    if (nsteps > 0) {
+        const AlphaBufs a0 = alpha_bufs_run(p, ws, 0);
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(a0.nfill, 256)), dim3(256), 0, ctx->stream, a0.ax, a0.nfill, 0.0);
+        HIP_TRY(hipGetLastError());
+    }
     for (int64_t k = 0; k < nsteps; ++k) {
         double* S[3] = {stages + (3 * k) * ns, stages + (3 * k + 1) * ns, stages + (3 * k + 2) * ns};
         uint8_t* ix = idx_log + (size_t)k * 3 * ib;
@@ -519,19 +525,23 @@ enomr_status record_steps(enomr_ctx* ctx, const enomr_problem& p, double* U, dou
         double* dt = dt_log + k;
         HIP_TRY(hipMemcpyAsync(S[0], U, sizeof(double) * ns, hipMemcpyDeviceToDevice, ctx->stream));
         double* outs[3] = {S[1], S[2], U};
-        for (int s = 0; s < 3; ++s) {
-            if (enomr_status st = launch_alpha(ctx, p, S[s], ws, nullptr)) return st;
-            hipLaunchKernelGGL(k_copy1, dim3(1), dim3(64), 0, ctx->stream, al + s, at<double>(ws, w.ax));
+        for (int s = 0; s < 3; ++s, ++run) {
+            const AlphaBufs ab = alpha_bufs_run(p, ws, run);
+            const AlphaBufs next = alpha_bufs_run(p, ws, run + 1);
+            if (enomr_status st = launch_alpha(ctx, p, S[s], ab, nullptr, &next)) return st;
+            hipLaunchKernelGGL(k_copy1, dim3(1), dim3(64), 0, ctx->stream, al + s, ab.ax);
             HIP_TRY(hipGetLastError());
             if (s == 0)
-                if (enomr_status st = launch_dt(ctx, p, cfl, ws, alpha_bufs(p, ws), dt, 0.0, nullptr, 0)) return st;
+                if (enomr_status st = launch_dt(ctx, p, cfl, ws, ab, dt, 0.0, nullptr, 0)) return st;
             StageOut so;
             so.Un = S[0];
             so.Lprev = nullptr;
             so.out = outs[s];
             so.dt = dt;
             so.stage = s + 1;
-            if (enomr_status st = launch_operator(ctx, p, S[s], so, ix + s * ib, ws, nullptr)) return st;
+            if (enomr_status st = launch_operator(ctx, p, S[s], so, ix + s * ib, ab, at<double>(ws, layout(p).L),
+                                                  nullptr))
+                return st;
         }
     }
     return ENOMR_OK;
