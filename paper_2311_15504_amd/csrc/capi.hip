@@ -320,7 +320,9 @@ enomr_status launch_alpha(enomr_ctx* ctx, const enomr_problem& p, const double* 
                 hipLaunchKernelGGL(k_alpha_euler<3>, grid, dim3(256), 0, ctx->stream, Us, (long)p.nx, (long)p.ny,
                                    p.gamma, ax, ay, ctx->status, active, zp, zn);
         } else {
-            const unsigned nb = blocks_for(p.nx, 256) < 64 ? blocks_for(p.nx, 256) : 64;
+            // a few thousand workgroups of eight cells per thread (a pass over
+            // the line for Burgers; advection needs none)
+            const unsigned nb = blocks_for(p.nx, 256 * 8) < 2048 ? blocks_for(p.nx, 256 * 8) : 2048;
             hipLaunchKernelGGL(k_alpha_scalar, dim3(nb), dim3(256), 0, ctx->stream, Us, (long)p.nx,
                                p.system == ENOMR_ADVECTION ? SYS_ADVECTION : SYS_BURGERS, p.adv_speed, ax, active);
         }

@@ -70,14 +70,19 @@ __global__ void k_set_int(int* p, int v)
     if (threadIdx.x == 0) *p = v;
 }
 
-// Scalar laws: alpha = max |f'(u)| over the line (|a| or max |u|).
+// Scalar laws: alpha = max |f'(u)| over the line: |a| for advection (no
+// pass over the line), max |u| for Burgers.
 __global__ void k_alpha_scalar(const double* __restrict__ u, long n, int flux, double a,
                                double* alpha, const int* active)
 {
     if (active && *active == 0) return;
+    if (flux == SYS_ADVECTION) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) atomic_max_nonneg(alpha, fabs(a));
+        return;
+    }
     double m = 0.0;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        m = fmax(m, flux == SYS_ADVECTION ? fabs(a) : fabs(u[i]));
+        m = fmax(m, fabs(u[i]));
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) atomic_max_nonneg(alpha, m);
 }
