@@ -58,6 +58,26 @@ def build_sanitized(out_dir, verbose=False):
     return lib
 
 
+def build_phase_stamps(verbose=False):
+    """libenomr_phases.so next to the library: the same sources with
+    ENOMR_PHASE_STAMPS defined, so the 2D x-face sweep records per-wave phase
+    stamps (phase_stamps.py reads them).  Not the library the binding loads."""
+    out = os.path.join(HERE, "libenomr_phases.so")
+    tmp = os.path.join(HERE, "_build", "phases")
+    os.makedirs(tmp, exist_ok=True)
+    objs = []
+    for src, lang in (("tables.cpp", ["-x", "hip"]), ("capi.hip", [])):
+        obj = os.path.join(tmp, src.split(".")[0] + ".o")
+        cmd = [HIPCC] + lang + ["-c", os.path.join(CSRC, src), "-o", obj, "-DENOMR_PHASE_STAMPS"] + COMMON + DEVICE
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    subprocess.check_call([HIPCC, "-shared", "-o", out + ".tmp"] + objs + DEVICE + ["-fPIC"])
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def asan_runtime():
     """The AddressSanitizer runtime of hipcc's host compiler (to preload)."""
     out = subprocess.check_output([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
@@ -88,4 +108,7 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    if "--phase-stamps" in sys.argv:
+        build_phase_stamps(verbose="-v" in sys.argv)
+    else:
+        build(verbose="-v" in sys.argv)

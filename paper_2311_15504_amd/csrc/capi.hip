@@ -19,6 +19,9 @@ __constant__ double c_a[kPool][kMaxW];
 __constant__ double c_wa[2][kPool][kMaxW];
 __constant__ int c_candpool[10][kPool];
 __constant__ double c_wrow[10][kRowsMax];
+#ifdef ENOMR_PHASE_STAMPS
+__device__ unsigned long long g_phase_stamps[kStampBlocks * kStampWaves * kStampPhases];
+#endif
 
 // Device memory of enomr_rhs_noalloc, the entry point that allocates nothing:
 // the per-line alphas of one operator evaluation.  Each device the library
@@ -1521,3 +1524,16 @@ enomr_status enomr_batch_destroy(enomr_batch* b)
 }
 
 }  // extern "C"
+
+#ifdef ENOMR_PHASE_STAMPS
+// Instrumented builds only: the phase stamps of the last x-face sweep launch
+// (kStampBlocks workgroups x kStampWaves waves x kStampPhases stamps, in that
+// order) into `host`, which holds `count` of them.
+extern "C" enomr_status enomr_phase_stamps(unsigned long long* host, size_t count)
+{
+    if (!host || count > (size_t)kStampBlocks * kStampWaves * kStampPhases) return fail(ENOMR_EINVAL, "bad buffer");
+    HIP_TRY(hipMemcpyFromSymbol(host, HIP_SYMBOL(enomr::g_phase_stamps), count * sizeof(unsigned long long), 0,
+                                hipMemcpyDeviceToHost));
+    return ENOMR_OK;
+}
+#endif

@@ -19,6 +19,31 @@
 namespace enomr {
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1 };
+
+// Phase stamps of the 2D x-face sweep, in an instrumented build only (compiled
+// with ENOMR_PHASE_STAMPS defined; the library's own build has none): lane 0
+// of each wave of the first kStampBlocks workgroups records the shader clock
+// (s_memtime) at every phase boundary of its tile (see sweep_tile), and
+// enomr_phase_stamps copies the records to the host.  Stamp 1 waits for the
+// tile's loads, which the uninstrumented kernel does a little later.
+constexpr int kStampBlocks = 20000, kStampWaves = 4, kStampPhases = 10;
+#ifdef ENOMR_PHASE_STAMPS
+extern __device__ unsigned long long g_phase_stamps[kStampBlocks * kStampWaves * kStampPhases];
+#endif
+template <int NV, int DIR>
+__device__ __forceinline__ void phase_stamp(int k)
+{
+#ifdef ENOMR_PHASE_STAMPS
+    if constexpr (NV == 4 && DIR == 0) {
+        if (k == 1) __builtin_amdgcn_s_waitcnt(0);
+        if ((threadIdx.x & 63) == 0 && blockIdx.x < kStampBlocks && (threadIdx.x >> 6) < kStampWaves)
+            g_phase_stamps[(blockIdx.x * kStampWaves + (threadIdx.x >> 6)) * kStampPhases + k] =
+                __builtin_amdgcn_s_memtime();
+    }
+#else
+    (void)k;
+#endif
+}
 enum { SYS_ADVECTION = 0, SYS_BURGERS = 1 };
 
 __device__ __forceinline__ long map_cell(long i, long n, int bc)
@@ -823,6 +848,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     constexpr int NROW = (n_cands(R) - 4) * W;
     constexpr int NRIT = (NROW + NT - 1) / NT;
     double rowv[NRIT];
+    phase_stamp<NV, DIR>(0);   // tile start
     __builtin_amdgcn_s_setprio(2);   // issue this tile's loads ahead of other waves' arithmetic
 #pragma unroll
     for (int it = 0; it < NRIT; ++it) {
@@ -843,6 +869,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         }
     }
     __builtin_amdgcn_s_setprio(0);
+    phase_stamp<NV, DIR>(1);   // the tile's loads have arrived
 #pragma unroll
     for (int it = 0; it < NRIT; ++it) {
         const int e = threadIdx.x + it * NT;
@@ -893,7 +920,9 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             sm.H[lp] = (E + p) * ir;
         }
     }
+    phase_stamp<NV, DIR>(2);   // staged
     __syncthreads();
+    phase_stamp<NV, DIR>(3);   // the whole tile staged
 
     // Which face a lane takes.  x faces: a wavefront covers FW consecutive
     // faces of 64/FW neighbouring lines (a block rather than a strip of 64
@@ -1078,6 +1107,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         // ---- remaining candidates for the (field, sign) pairs that failed;
         // the pair index is uniform across the wave, so each pass runs code
         // specialised to its field and sign
+        phase_stamp<NV, DIR>(4);   // eigenvectors and the full stencil of every pair done
         if (fail) {
 #pragma unroll 1
             for (int kk = 0; kk < 2 * NV; ++kk) {
@@ -1110,6 +1140,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             }
         }
 
+        phase_stamp<NV, DIR>(5);   // fallback done
         double wh[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) wh[q] = hp[q] + hm[q];
@@ -1152,11 +1183,13 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             s_rv = in.Us[2 * plane + g];
         }
     }
+    phase_stamp<NV, DIR>(6);   // face flux and the output operands requested
     __syncthreads();   // every fallback is done with the candidate rows
     if (live) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) sm.F[q * NT + fpos(tl, tf)] = Fh[q];
     }
+    phase_stamp<NV, DIR>(7);   // face fluxes written
     __syncthreads();
     if (outc) {
 #pragma unroll
@@ -1172,6 +1205,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             else so.out[v * plane + g] = rk_combine(so.stage, un[q], us[q], L, dt);
         }
     }
+    phase_stamp<NV, DIR>(8);   // output stored
 }
 
 // Workgroups are handed to the XCDs round-robin by linear id, and each XCD has
