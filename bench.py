@@ -11,6 +11,7 @@ wall time), the roofline of the dominant kernel (FP64 vector ALU), and the CPU
 oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import functools
 import json
 import re
 import os
@@ -51,6 +52,7 @@ SUM_OPS = NV                 # L_x + L_y
 RK_OPS = {1: 2 * NV, 2: 5 * NV, 3: 5 * NV}   # the SSP-RK3 stage combination
 
 
+@functools.lru_cache(maxsize=None)
 def _pair_tables(order):
     """Ops and fma ops of one (field, sign) reconstruction by its logged
     candidate C: IS0, the b_l chain and compare of every candidate tested in
@@ -103,14 +105,15 @@ def stage_tail_ops(ncells, rk_stage):
     return ncells * (SUM_OPS + RK_OPS[rk_stage])
 
 
-def _hists(log, n, ib):
+def _hists(log, n, ib, ny=None):
     """Per-field candidate histograms ([4][256]) of the x and y faces of one
-    stage's log (x faces [ny][nx+1][4][2], face nx repeating face 0 of a
-    periodic row; y faces [ny+1][nx][4][2])."""
+    stage's log of an n x ny problem (x faces [ny][n+1][4][2], face n
+    repeating face 0 of a periodic row; y faces [ny+1][n][4][2])."""
     import torch
-    nxf = n * (n + 1) * 8
-    xs = log[:nxf].view(n, n + 1, 4, 2)[:, :n]
-    ys = log[nxf:ib].view(n + 1, n, 4, 2)
+    ny = n if ny is None else ny
+    nxf = ny * (n + 1) * 8
+    xs = log[:nxf].view(ny, n + 1, 4, 2)[:, :n]
+    ys = log[nxf:ib].view(ny + 1, n, 4, 2)
     hx = torch.stack([torch.bincount(xs[:, :, q, :].reshape(-1).long(), minlength=256)[:256] for q in range(4)])
     hy = torch.stack([torch.bincount(ys[:, :, q, :].reshape(-1).long(), minlength=256)[:256] for q in range(4)])
     return hx.double(), hy.double()
@@ -364,6 +367,31 @@ def run_batched_2d(args):
     cells_pp = sum(plist[i]["nx"] * plist[i]["ny"] for i in sample)
     value_pp = cells_pp * 3 * steps / (ms_pp * 1e-3)
     same = all(torch.equal(states[i], Us[k]) for k, i in enumerate(sample))
+    # Algorithmic work of the timed steps (the operation count above: pair,
+    # face, line and stage-tail operations), estimated from the sample: its problems' own runs of the same steps
+    # repeated with stencil logs give each order's operations per cell and
+    # stage, which are applied to every problem of that order.
+    ops_o, cells_o = {}, {}
+    for i in sample:
+        p, pr = plist[i], probs[i]
+        nx, ny, order = p["nx"], p["ny"], p["order"]
+        U = torch.from_numpy(host[i]).cuda()
+        ib = pr.idx_bytes()
+        log = torch.empty(3 * ib, dtype=torch.uint8, device="cuda")
+        ops = 0.0
+        for _ in range(steps):
+            dt = ctx.dt(pr, U, cfl)
+            ctx.ssprk3_step(pr, U, dt, log)
+            for s in range(3):
+                hxs, hys = _hists(log[s * ib:(s + 1) * ib], nx, ib, ny)
+                ops += line_ops(order, nx * ny, nx * ny, hxs.cpu().numpy())[0] + stage_tail_ops(nx * ny, s + 1)
+                ops += line_ops(order, (ny + 1) * nx, nx * ny, hys.cpu().numpy())[0]
+        ops_o[order] = ops_o.get(order, 0.0) + ops
+        cells_o[order] = cells_o.get(order, 0) + nx * ny * 3 * steps
+    ctx.check()
+    per_cell = {o: ops_o[o] / cells_o[o] for o in ops_o}
+    total_ops = sum(per_cell[p["order"]] * p["nx"] * p["ny"] * 3 * steps for p in plist if p["order"] in per_cell)
+    achieved = total_ops / (ms * 1e-3)
     batch.close()
     ctx.close()
     return {"workload": "%d independent 2D Euler problems, nx, ny ~ U{32..%d}, orders {7,9,13,17}, seeded "
@@ -373,7 +401,13 @@ def run_batched_2d(args):
             "workgroups": info["workgroups"], "tile2d": list(info["tile2d"]),
             "autotune_ms_per_step": {"%dx%d" % sh: t for sh, t in zip(((64, 4), (32, 8), (16, 16)), info["tune2d_ms"])},
             "per_problem_launches": {"value": value_pp, "sample_problems": int(len(sample)), "ms": ms_pp},
-            "speedup_vs_per_problem": value / value_pp, "sample_bitwise_equal": bool(same)}
+            "speedup_vs_per_problem": value / value_pp, "sample_bitwise_equal": bool(same),
+            "work": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
+                     "unit": "Top/s (FP64 vector ops, fma = 1)", "frac": achieved / PEAK_FP64_OPS,
+                     "ops_per_cell_stage": {str(o): per_cell[o] for o in sorted(per_cell)},
+                     "rule": "the whole batch's timed steps against the method's operation count (the 2D workload's "
+                             "rule), counted per order from stencil logs of the sampled problems' own runs of "
+                             "the same steps"}}
 
 
 SCALAR_BYTES_PER_CELL_STAGE = 64.0 / 3.0   # read U^(s), read U^n (stages 2, 3), write U^(s+1)
