@@ -162,6 +162,52 @@ __device__ __forceinline__ double select_rest(const double (&w)[2 * R - 1], doub
     return minmod_flux<R, S>(w, idx);
 }
 
+// The whole scalar reconstruction (Steps 1-3.2) of the window w[0 .. 2R-2]
+// read where it lies (the LDS tile of a sweep), bitwise the same as recon():
+// the full stencil's indicator and flux chains stream the window (the flux
+// chain is kept only if the indicator passes), and only a window that fails
+// is copied into registers for its difference table.  Holding no window in
+// registers on the smooth path leaves room for more waves per SIMD.
+template <int R, int S>
+__device__ __forceinline__ double recon_streamed(const double* w, int& idx)
+{
+    constexpr int P0 = cand_pool(R, 0);
+    constexpr int W = 2 * R - 1;
+    const double f0 = w[R - 1];
+    const double fm1 = S > 0 ? w[R - 2] : w[R];
+    const double fm2 = S > 0 ? w[R - 3] : w[R + 1];
+    const double fp1 = S > 0 ? w[R] : w[R - 2];
+    const double fp2 = S > 0 ? w[R + 1] : w[R - 3];
+    const double isl = fmax(fabs(f0 - fm1), fabs(fma(-2.0, fm1, f0) + fm2));
+    const double isr = fmax(fabs(f0 - fp1), fabs(fma(-2.0, fp1, f0) + fp2));
+    const double is0 = fmin(isl, isr);
+    double is = kCoef.b[P0][coef_index<R, S, R - 1>(0)] * w[0];
+    double fl = kCoef.a[P0][coef_index<R, S, R - 1>(0)] * w[0];
+#pragma unroll
+    for (int i = 1; i < W; ++i) {
+        const double x = w[i];
+        is = fma(kCoef.b[P0][coef_index<R, S, R - 1>(i)], x, is);
+        fl = fma(kCoef.a[P0][coef_index<R, S, R - 1>(i)], x, fl);
+    }
+    if (fabs(is) < is0) {
+        idx = 0;
+        return fl;
+    }
+    double d[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) d[i] = w[i];
+    const int c = first_passing<R, S>(d, is0);
+    if (c >= 0) {
+        idx = c;
+        const double* wa = &c_wa[S > 0 ? 0 : 1][c_candpool[R][c]][9 - R];
+        double f = wa[0] * w[0];
+#pragma unroll
+        for (int i = 1; i < W; ++i) f = fma(wa[i], w[i], f);
+        return f;
+    }
+    return minmod3<R>(f0, fp1, fm1, idx);
+}
+
 // The whole scalar reconstruction (Steps 1-3.2) of one window.
 template <int R, int S>
 __device__ __forceinline__ double recon(const double (&w)[2 * R - 1], int& idx)

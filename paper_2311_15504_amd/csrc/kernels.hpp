@@ -348,16 +348,11 @@ __global__ __launch_bounds__(TF) void k_scalar_sweep(const double* __restrict__ 
     const long face = c0 + tf;
     if (face <= n) {
         const int jp = tf + R - 1;   // left cell of the face in LDS
-        double wp[2 * R - 1], wm[2 * R - 1];
-#pragma unroll
-        for (int k = 0; k < 2 * R - 1; ++k) {
-            wp[k] = sp[jp - (R - 1) + k];
-            wm[k] = sm[jp - (R - 2) + k];
-        }
+        // the windows are read from the LDS tile as the reconstruction runs
         int ip, im = 0;
-        const double hp = recon<R, +1>(wp, ip);
+        const double hp = recon_streamed<R, +1>(sp + jp - (R - 1), ip);
         double hm = 0.0;
-        if (split) hm = recon<R, -1>(wm, im);
+        if (split) hm = recon_streamed<R, -1>(sm + jp - (R - 2), im);
         sf[tf] = hp + hm;
         if (idx) {
             idx[2 * face] = (uint8_t)ip;
