@@ -112,3 +112,61 @@ def test_variants_are_rejected_where_unsupported(ctx):
     with pytest.raises(enomr.EnomrError) as e:
         ctx.record_steps(p, _dev(U), 0.5, 2, stages, idx, alpha, dts)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("dim,kw", [(1, dict()), (1, dict(componentwise=True)), (1, dict(per_field=True)),
+                                    (2, dict()), (2, dict(componentwise=True)), (2, dict(per_field=True)),
+                                    (2, dict(gravity=1.0))],
+                         ids=["1d", "1d-componentwise", "1d-per_field", "2d", "2d-componentwise", "2d-per_field",
+                              "2d-gravity"])
+def test_advance_equals_single_steps(ctx, dim, kw):
+    # enomr_advance alternates its stages between two alpha buffers, each
+    # alpha pass zeroing the next stage's; single steps fill the one buffer
+    # before every alpha pass.  Both give the same run bit for bit (dt of each
+    # step from the CFL rule either way).
+    import paper_2311_15504_amd as enomr
+    order, nsteps = 9, 7
+    if dim == 1:
+        n = 700
+        _, h, U0 = workloads.euler1d_riemann_perturbed(21, n)
+        prob = enomr.Problem.euler1d(n, h, order, **kw)
+    else:
+        nx, ny = 130, 90
+        (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(22, nx, ny)
+        prob = enomr.Problem.euler2d(nx, ny, hx, hy, order, **kw)
+    A = _dev(U0)
+    ctx.advance(prob, A, 0.5, nsteps)
+    B = _dev(U0)
+    for _ in range(nsteps):
+        dt = ctx.dt(prob, B, 0.5)
+        ctx.ssprk3_step(prob, B, dt)
+    ctx.check()
+    assert np.array_equal(_host(A), _host(B))
+
+
+def test_advance_to_an_end_time_equals_single_steps(ctx):
+    # With an end time the run's step that would pass it is shortened and the
+    # later steps do nothing (every kernel of the run checks the active flag,
+    # the alternating alpha buffers included): the same states as single steps
+    # with the logged step sizes.
+    import torch
+    import paper_2311_15504_amd as enomr
+    nx, ny, order, nsteps = 120, 100, 13, 12
+    (x, y, hx, hy), U0 = workloads.euler2d_quadrants_vortices(23, nx, ny)
+    prob = enomr.Problem.euler2d(nx, ny, hx, hy, order)
+    probe = _dev(U0)
+    dt0 = float(_host(ctx.dt(prob, probe, 0.5))[0])
+    t_end = 6.5 * dt0                               # ends inside a step, well before nsteps
+    A = _dev(U0)
+    log = torch.zeros(nsteps, dtype=torch.float64, device="cuda")
+    ctx.advance(prob, A, 0.5, nsteps, t_end=t_end, dt_log=log)
+    ctx.check()
+    dts = _host(log)
+    k = int(np.count_nonzero(dts))
+    assert 6 <= k < nsteps and np.all(dts[k:] == 0.0)
+    assert abs(dts[:k].sum() - t_end) <= 1e-13 * t_end
+    B = _dev(U0)
+    for j in range(k):
+        ctx.ssprk3_step(prob, B, log[j:j + 1])
+    ctx.check()
+    assert np.array_equal(_host(A), _host(B))
