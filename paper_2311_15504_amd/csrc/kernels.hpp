@@ -465,6 +465,7 @@ __global__ __launch_bounds__(256) void k_scalar_sweep_dpp(const double* __restri
     const bool aligned = (((uintptr_t)us | (uintptr_t)so.out | (so.stage ? (uintptr_t)so.Un : 0)) & 15) == 0;
     const bool inner = aligned && base >= 0 && base + 64 * KC <= n;
     const double al = split ? *alpha : 0.0;
+    const double dt = so.stage ? *so.dt : 0.0;   // requested with the cells, used at the end
     // own cells c0 .. c0+KC-1; the stage's U^n at the same cells
     double u[KC], un[KC];
     if (inner) {
@@ -523,7 +524,6 @@ __global__ __launch_bounds__(256) void k_scalar_sweep_dpp(const double* __restri
         fh[j] = hp + hm;
     }
     const double fnext = from_right(fh[0]);   // the next lane's first face
-    const double dt = so.stage ? *so.dt : 0.0;
     double res[KC];
     bool ok[KC];
 #pragma unroll
