@@ -22,26 +22,63 @@ enum { BC_PERIODIC = 0, BC_OUTFLOW = 1 };
 
 // Phase stamps of the 2D x-face sweep, in an instrumented build only (compiled
 // with ENOMR_PHASE_STAMPS defined; the library's own build has none): lane 0
-// of each wave of the first kStampBlocks workgroups records the shader clock
-// (s_memtime) at every phase boundary of its tile (see sweep_tile), and
-// enomr_phase_stamps copies the records to the host.  Stamp 1 waits for the
-// tile's loads, which the uninstrumented kernel does a little later.
-constexpr int kStampBlocks = 20000, kStampWaves = 4, kStampPhases = 10;
+// of each wave of the first kStampBlocks workgroups records, in its record of
+// kStampPhases words,
+//   0..8   the shader clock (s_memtime) at every phase boundary of its tile
+//          (see sweep_tile); stamp 1 waits for the tile's loads, which the
+//          uninstrumented kernel does a little later;
+//   9, 10  the real-time clock (s_memrealtime, 100 MHz, one count for the
+//          whole device, unlike the shader clock) at the tile's start and
+//          after its stores are issued;
+//   11     the wave's hardware position: HW_ID (CU, shader engine, SIMD) in
+//          the low word, the XCD (XCC_ID) in the high word;
+//   12     the real-time clock at the kernel's entry;
+//   13     the real-time clock once the tile's stores are acknowledged (the
+//          wave waits for them here);
+// and enomr_phase_stamps copies the records to the host.
+constexpr int kStampBlocks = 20000, kStampWaves = 4, kStampPhases = 14;
 #ifdef ENOMR_PHASE_STAMPS
 extern __device__ unsigned long long g_phase_stamps[kStampBlocks * kStampWaves * kStampPhases];
+__device__ __forceinline__ unsigned long long* stamp_record()
+{
+    if ((threadIdx.x & 63) != 0 || blockIdx.x >= kStampBlocks || (threadIdx.x >> 6) >= kStampWaves) return nullptr;
+    return g_phase_stamps + (blockIdx.x * kStampWaves + (threadIdx.x >> 6)) * kStampPhases;
+}
 #endif
 template <int NV, int DIR>
 __device__ __forceinline__ void phase_stamp(int k)
 {
 #ifdef ENOMR_PHASE_STAMPS
     if constexpr (NV == 4 && DIR == 0) {
+        // s_getreg operands: register id | offset << 6 | (bits - 1) << 11
+        constexpr int kHwId = 4 | (31 << 11), kXccId = 20 | (3 << 11);
         if (k == 1) __builtin_amdgcn_s_waitcnt(0);
-        if ((threadIdx.x & 63) == 0 && blockIdx.x < kStampBlocks && (threadIdx.x >> 6) < kStampWaves)
-            g_phase_stamps[(blockIdx.x * kStampWaves + (threadIdx.x >> 6)) * kStampPhases + k] =
-                __builtin_amdgcn_s_memtime();
+        if (unsigned long long* q = stamp_record()) {
+            q[k] = __builtin_amdgcn_s_memtime();
+            if (k == 0) {
+                q[9] = __builtin_amdgcn_s_memrealtime();
+                q[11] = (unsigned long long)(unsigned)__builtin_amdgcn_s_getreg(kHwId) |
+                        ((unsigned long long)(unsigned)__builtin_amdgcn_s_getreg(kXccId) << 32);
+            }
+            if (k == 8) {
+                q[10] = __builtin_amdgcn_s_memrealtime();
+                __builtin_amdgcn_s_waitcnt(0);
+                q[13] = __builtin_amdgcn_s_memrealtime();
+            }
+        }
     }
 #else
     (void)k;
+#endif
+}
+// The kernel's entry (record word 12), instrumented build only.
+template <int NV, int DIR>
+__device__ __forceinline__ void entry_stamp()
+{
+#ifdef ENOMR_PHASE_STAMPS
+    if constexpr (NV == 4 && DIR == 0) {
+        if (unsigned long long* q = stamp_record()) q[12] = __builtin_amdgcn_s_memrealtime();
+    }
 #endif
 }
 enum { SYS_ADVECTION = 0, SYS_BURGERS = 1 };
@@ -579,7 +616,7 @@ struct Eig {
     double a0, a1, a3, a4;   // first two entries of the u-c and u+c rows of L
     double C, D;             // last entries shared by those rows: -k v/2, k/2
     double l20, ku, kv, k;   // the u row of L: (1 - k q^2/2, k u, k v, -k)
-    double u, v, c, H, uc, q2h;
+    double u, v, c, H;       // the Roe state, for R
 };
 
 template <int NV>
@@ -612,8 +649,6 @@ __device__ __forceinline__ bool roe_eigen(double sL, double unL, double utL, dou
     e.v = v;
     e.c = c;
     e.H = H;
-    e.uc = u * c;
-    e.q2h = 0.5 * q2;
     return c2 > 0.0;
 }
 
@@ -658,17 +693,24 @@ __device__ __forceinline__ double project_row(const Eig& e, const double (&G)[NV
 template <int NV>
 __device__ __forceinline__ void back_project(const Eig& e, const double (&w)[NV], double (&F)[NV])
 {
-    const double umc = e.u - e.c, upc = e.u + e.c;
-    const double hm = e.H - e.uc, hp = e.H + e.uc;
+    // u c and q^2/2 from the Roe state again, with the expressions of
+    // roe_eigen (the same values); the state passes an empty asm first so
+    // that they are formed here, not held from the projection onwards
+    double u = e.u, v = e.v, c = e.c;
+    asm volatile("" : "+v"(u), "+v"(v), "+v"(c));
+    const double uc = u * c;
+    const double q2h = 0.5 * (NV == 4 ? u * u + v * v : u * u);
+    const double umc = u - c, upc = u + c;
+    const double hm = e.H - uc, hp = e.H + uc;
     if constexpr (NV == 4) {
         F[0] = (w[0] + w[1]) + w[3];
-        F[1] = fma(upc, w[3], fma(e.u, w[1], umc * w[0]));
-        F[2] = fma(e.v, w[3], fma(e.v, w[1], e.v * w[0]) + w[2]);
-        F[3] = fma(hp, w[3], fma(e.v, w[2], fma(e.q2h, w[1], hm * w[0])));
+        F[1] = fma(upc, w[3], fma(u, w[1], umc * w[0]));
+        F[2] = fma(v, w[3], fma(v, w[1], v * w[0]) + w[2]);
+        F[3] = fma(hp, w[3], fma(v, w[2], fma(q2h, w[1], hm * w[0])));
     } else {
         F[0] = (w[0] + w[1]) + w[2];
-        F[1] = fma(upc, w[2], fma(e.u, w[1], umc * w[0]));
-        F[2] = fma(hp, w[2], fma(e.q2h, w[1], hm * w[0]));
+        F[1] = fma(upc, w[2], fma(u, w[1], umc * w[0]));
+        F[2] = fma(hp, w[2], fma(q2h, w[1], hm * w[0]));
     }
 }
 
@@ -928,9 +970,11 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     constexpr int FW = TL >= 4 ? 16 : 64 / TL;   // x faces: faces per wavefront row
     constexpr int LW = 64 / FW;                  // x faces: lines per wavefront
     static_assert(DIR == 1 || (TL % LW == 0 && TF % FW == 0 && NT % 64 == 0), "x-face wavefront shape");
-    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
-    const int tf = DIR == 0 ? (wv / (TL / LW)) * FW + ln % FW : threadIdx.x / TL;
-    const int tl = DIR == 0 ? (wv % (TL / LW)) * LW + ln / FW : threadIdx.x % TL;
+    // thread t -> face and line of the tile (wave t / 64, lane t % 64)
+    auto lane_face = [](int t) { return DIR == 0 ? ((t / 64) / (TL / LW)) * FW + (t % 64) % FW : t / TL; };
+    auto lane_line = [](int t) { return DIR == 0 ? ((t / 64) % (TL / LW)) * LW + (t % 64) / FW : t % TL; };
+    const int tf = lane_face(threadIdx.x);
+    const int tl = lane_line(threadIdx.x);
     const long gl = line0 + tl;
     const long face = c0 + tf;
     const bool live = gl < nlines && face <= n;
@@ -1147,8 +1191,13 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         }
 
         if (in.idx) {
-            uint8_t* dst = DIR == 0 ? in.idx + ((gl * (n + 1) + face) * NV) * 2
-                                    : in.idx + ((face * nx + gl) * NV) * 2;
+            // the face's line and position from the thread index again
+            // (through an empty asm), not held through the reconstruction
+            int t = threadIdx.x;
+            asm volatile("" : "+v"(t));
+            const long il = line0 + lane_line(t), ifc = c0 + lane_face(t);
+            uint8_t* dst = DIR == 0 ? in.idx + ((il * (n + 1) + ifc) * NV) * 2
+                                    : in.idx + ((ifc * nx + il) * NV) * 2;
 #pragma unroll
             for (int b = 0; b < 2 * NV; ++b) dst[b] = (uint8_t)(idxw >> (8 * b));
         }
@@ -1225,6 +1274,7 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb)
 template <int NV, int R, int DIR, int TF, int TL, int VAR = VAR_CHAR>
 __global__ __launch_bounds__(TF* TL, 4) void k_euler_sweep(SweepIn in, StageOut so)
 {
+    entry_stamp<NV, DIR>();
     if (in.active && *in.active == 0) return;
     constexpr int NCL = TF + 2 * R - 1;
     __shared__ SweepLds<NV, NCL * TL, TF * TL> lds;

@@ -3,11 +3,17 @@
 Loads libenomr_phases.so, the library built with ENOMR_PHASE_STAMPS
 (`python3 paper_2311_15504_amd/build.py --phase-stamps`), evaluates the
 operator of the seeded quadrants + vortices state a few times, and reads the
-shader-clock stamps lane 0 of every wave of the last x-face sweep recorded at
-its tile's phase boundaries.  Prints a markdown summary: per phase the mean,
-median and 90th percentile over the waves, in cycles of the shader clock, and
-the fallback's mean and per-workgroup maximum over the four waves (the
-workgroup's barrier waits for the slowest).
+stamps lane 0 of every wave of the last x-face sweep recorded.  Prints a
+markdown summary:
+  - per phase of a tile the mean, median and 90th percentile over the waves,
+    in cycles of the shader clock, and the fallback's mean and per-workgroup
+    maximum over the four waves (the workgroup's barrier waits for the
+    slowest);
+  - from the real-time clock and the hardware position of each workgroup:
+    how many workgroups are resident on average against the slots the
+    launch has (4 per CU), the time from one workgroup's end to the next
+    one's start on the same CU, the kernel's prologue, and the tail (CUs
+    idle after their last workgroup while others finish).
 
 usage: python3 -m paper_2311_15504_amd.phase_stamps [order] [--command TEXT]
 """
@@ -34,7 +40,9 @@ PHASES = [
     ("barrier: every fallback of the tile done", 6, 7),
     ("face fluxes to LDS, barrier, difference, RK stage, store", 7, 8),
 ]
-BLOCKS, WAVES, NSTAMP = 20000, 4, 10
+BLOCKS, WAVES, NSTAMP = 20000, 4, 14
+RT_NS = 10.0   # the real-time clock runs at 100 MHz
+SLOTS_PER_CU = 4
 
 
 def main(argv):
@@ -101,7 +109,59 @@ def main(argv):
     full = ok.all(axis=1)
     lines += ["", "Fallback per workgroup (workgroups whose four waves have every stamp): mean over its waves "
               "%.0f cycles, the slowest wave %.0f." % (fb[full].mean(axis=1).mean(), fb[full].max(axis=1).mean())]
+    lines += [""] + turnover(buf.reshape(BLOCKS, WAVES, NSTAMP)[:nblocks].astype(np.int64))
     print("\n".join(lines))
+
+
+def turnover(r):
+    """Workgroup residency from the real-time stamps of every wave (words 9,
+    10, 12, 13 of a record) and its hardware position (word 11)."""
+    entry = r[:, :, 12].min(axis=1)          # first wave enters the kernel
+    start = r[:, :, 9].min(axis=1)           # tile start
+    done = r[:, :, 13].max(axis=1)           # the last wave's stores acknowledged
+    issued = r[:, :, 10].max(axis=1)         # the last wave's stores issued
+    hw = r[:, 0, 11]
+    hwid, xcc = hw & 0xFFFFFFFF, (hw >> 32) & 0xF
+    cu = xcc * 256 + ((hwid >> 13) & 0x7) * 32 + ((hwid >> 12) & 1) * 16 + ((hwid >> 8) & 0xF)
+    cus = np.unique(cu)
+    t0, t1 = entry.min(), done.max()
+    # resident workgroups over time, entry to stores acknowledged
+    ev = np.concatenate([np.stack([entry, np.ones_like(entry)], 1), np.stack([done, -np.ones_like(done)], 1)])
+    ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]
+    cnt = np.cumsum(ev[:, 1])
+    dt = np.diff(ev[:, 0])
+    slots = SLOTS_PER_CU * len(cus)
+    avg = (cnt[:-1] * dt).sum() / dt.sum()
+    gaps, spans = [], []
+    for c in cus:
+        m = cu == c
+        nxt = np.sort(entry[m])
+        spans.append(done[m].max() - entry[m].min())
+        for d in done[m]:
+            i = np.searchsorted(nxt, d)
+            if i < len(nxt):
+                gaps.append(nxt[i] - d)
+    gaps = np.array(gaps, dtype=np.float64) * RT_NS
+    life = (done - entry).astype(np.float64) * RT_NS
+    pro = (start - entry).astype(np.float64) * RT_NS
+    ack = (done - issued).astype(np.float64) * RT_NS
+    span = (t1 - t0) * RT_NS
+    spans = np.array(spans, dtype=np.float64) * RT_NS
+    return [
+        "Workgroup residency (real-time clock, 100 MHz; %d workgroups on %d CUs, %d slots):" % (len(entry), len(cus), slots),
+        "",
+        "| quantity | value |",
+        "|---|---|",
+        "| kernel span, first entry to last stores acknowledged | %.1f us |" % (span / 1e3),
+        "| workgroups resident, time average | %.0f of %d (%.1f%%) |" % (avg, slots, 100.0 * avg / slots),
+        "| workgroup life, entry to stores acknowledged (mean) | %.2f us |" % (life.mean() / 1e3),
+        "| of which prologue, entry to tile start (mean / median) | %.0f / %.0f ns |" % (pro.mean(), np.median(pro)),
+        "| of which the last wave's stores issued to acknowledged (mean) | %.0f ns |" % ack.mean(),
+        "| end of a workgroup to the next one's entry on the same CU (mean / median / 90th pct) | %.0f / %.0f / %.0f ns |"
+        % (gaps.mean(), np.median(gaps), np.percentile(gaps, 90)),
+        "| CU busy span, first entry to last end, mean over CUs (min / max) | %.1f us (%.1f / %.1f) |"
+        % (spans.mean() / 1e3, spans.min() / 1e3, spans.max() / 1e3),
+    ]
 
 
 if __name__ == "__main__":
