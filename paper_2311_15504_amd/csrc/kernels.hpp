@@ -853,10 +853,15 @@ __device__ __forceinline__ double fallback_window(const Eig& e, const double (&A
 // (rho, n, m, E) so that the same x-normal formulas apply.  NCL >= TF+2R-1 is
 // the number of cells per line the LDS holds.  VAR selects the operator variant (VAR_CHAR,
 // VAR_COMPONENT, VAR_FIELD).  All threads of the block must call it.
-template <int NV, int R, int DIR, int TF, int TL, int NCL, int VAR = VAR_CHAR>
+template <int NV, int R, int DIR, int TF, int TL, int NCL, int VAR = VAR_CHAR, bool LOOPED = false>
 __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so, long line0, long c0,
                                            SweepLds<NV, NCL * TL, TF * TL>& sm)
 {
+    // LOOPED: the caller runs tiles in a loop.  The thread index then passes
+    // an empty asm, so that the indices derived from it are formed per tile
+    // rather than hoisted out of the loop and held (spilled) through it.
+    int tid = threadIdx.x;
+    if constexpr (LOOPED) asm volatile("" : "+v"(tid));
     constexpr int NT = TF * TL;
     constexpr int TC = TF - 1;
     constexpr int NCU = TF + 2 * R - 1;   // cells staged per line
@@ -889,12 +894,12 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     __builtin_amdgcn_s_setprio(2);   // issue this tile's loads ahead of other waves' arithmetic
 #pragma unroll
     for (int it = 0; it < NRIT; ++it) {
-        const int e = threadIdx.x + it * NT;
+        const int e = tid + it * NT;
         if (e < NROW) rowv[it] = c_wrow[R][e];
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
-        const int e = threadIdx.x + it * NT;
+        const int e = tid + it * NT;
         const int line = DIR == 0 ? e / NCU : e % TL;
         const int cell = DIR == 0 ? e % NCU : e / TL;
         const long gl = line0 + line;
@@ -909,12 +914,12 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     phase_stamp<NV, DIR>(1);   // the tile's loads have arrived
 #pragma unroll
     for (int it = 0; it < NRIT; ++it) {
-        const int e = threadIdx.x + it * NT;
+        const int e = tid + it * NT;
         if (e < NROW) sm.F[e] = rowv[it];
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
-        const int e = threadIdx.x + it * NT;
+        const int e = tid + it * NT;
         const int line = DIR == 0 ? e / NCU : e % TL;
         const int cell = DIR == 0 ? e % NCU : e / TL;
         const long gl = line0 + line;
@@ -973,8 +978,8 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     // thread t -> face and line of the tile (wave t / 64, lane t % 64)
     auto lane_face = [](int t) { return DIR == 0 ? ((t / 64) / (TL / LW)) * FW + (t % 64) % FW : t / TL; };
     auto lane_line = [](int t) { return DIR == 0 ? ((t / 64) % (TL / LW)) * LW + (t % 64) / FW : t % TL; };
-    const int tf = lane_face(threadIdx.x);
-    const int tl = lane_line(threadIdx.x);
+    const int tf = lane_face(tid);
+    const int tl = lane_line(tid);
     const long gl = line0 + tl;
     const long face = c0 + tf;
     const bool live = gl < nlines && face <= n;
@@ -1193,7 +1198,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
         if (in.idx) {
             // the face's line and position from the thread index again
             // (through an empty asm), not held through the reconstruction
-            int t = threadIdx.x;
+            int t = tid;
             asm volatile("" : "+v"(t));
             const long il = line0 + lane_line(t), ifc = c0 + lane_face(t);
             uint8_t* dst = DIR == 0 ? in.idx + ((il * (n + 1) + ifc) * NV) * 2
@@ -1350,16 +1355,31 @@ __device__ __forceinline__ double block_max_speed(const double* __restrict__ U, 
     return r;
 }
 
+// A pointer that every lane holds the same value of, as a scalar.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (T*)(((unsigned long long)hi << 32) | lo);
+}
+
 template <int R, int TF>
-__device__ __forceinline__ void run_problem(const BatchProb& P, const BatchParams& prm, unsigned* status,
+__device__ __forceinline__ void run_problem(const BatchProb P, const BatchParams& prm, unsigned* status,
                                             char* lds_raw, double* red, double* s_alpha, double* s_dt)
 {
     using Lds = SweepLds<3, TF + 17, TF>;
     Lds& sm = *reinterpret_cast<Lds*>(lds_raw);
+    // the state and the two stage buffers as values (a stage picks two of
+    // them), not as fields of the descriptor in memory
+    double* const u0 = uniform_ptr(P.U);
+    double* const u1 = uniform_ptr(P.U1);
+    double* const u2 = uniform_ptr(P.U2);
     for (long step = 0; step < prm.nsteps; ++step) {
         for (int stage = 1; stage <= 3; ++stage) {
-            const double* Us = stage == 1 ? P.U : (stage == 2 ? P.U1 : P.U2);
-            double* out = stage == 1 ? P.U1 : (stage == 2 ? P.U2 : P.U);
+            const double* Us = stage == 1 ? u0 : (stage == 2 ? u1 : u2);
+            double* out = stage == 1 ? u1 : (stage == 2 ? u2 : u0);
             const double a = block_max_speed<TF>(Us, P.n, P.gamma, status, red);
             if (threadIdx.x == 0) {
                 *s_alpha = a;
@@ -1379,7 +1399,7 @@ __device__ __forceinline__ void run_problem(const BatchProb& P, const BatchParam
             in.grav = 0.0;
             in.bc = P.bc;
             StageOut so;
-            so.Un = P.U;
+            so.Un = u0;
             so.Lprev = nullptr;
             so.out = out;
             so.dt = s_dt;
@@ -1387,7 +1407,7 @@ __device__ __forceinline__ void run_problem(const BatchProb& P, const BatchParam
             // a tile's staging overwrites the face fluxes the previous tile's
             // output reads
             for (long c0 = 0; c0 < P.n; c0 += TF - 1) {
-                sweep_tile<3, R, 0, TF, 1, TF + 17>(in, so, 0, c0, sm);
+                sweep_tile<3, R, 0, TF, 1, TF + 17, VAR_CHAR, true>(in, so, 0, c0, sm);
                 __syncthreads();
             }
         }
@@ -1407,7 +1427,9 @@ __global__ __launch_bounds__(TF, 4) void k_batch_euler1d(const BatchProb* __rest
     for (;;) {
         if (threadIdx.x == 0) s_k = atomicAdd(queue, 1);
         __syncthreads();
-        const int k = s_k;
+        // the same value in every lane: read as a scalar, so that the
+        // problem's descriptor is loaded into scalar registers
+        const int k = __builtin_amdgcn_readfirstlane(s_k);
         __syncthreads();
         if (k >= nprob) return;   // the whole workgroup leaves together
         const BatchProb pr = probs[order[k]];
