@@ -889,6 +889,11 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     // the fluxes are written)
     constexpr int NROW = (n_cands(R) - 4) * W;
     constexpr int NRIT = (NROW + NT - 1) / NT;
+    // Where the face-flux area has room past the candidate rows, each face's
+    // Roe H and c wait there for the back-projection (their own slots, written
+    // and read by the same thread before the face fluxes overwrite the area)
+    // instead of in registers through the reconstruction.
+    constexpr bool STASH = VAR != VAR_COMPONENT && NROW + 2 * NT <= (int)(sizeof(sm.F) / sizeof(double));
     double rowv[NRIT];
     phase_stamp<NV, DIR>(0);   // tile start
     __builtin_amdgcn_s_setprio(2);   // issue this tile's loads ahead of other waves' arithmetic
@@ -993,6 +998,10 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
             const bool ok = roe_eigen<NV>(sm.Sq[pl], sm.Un[pl], NV == 4 ? sm.Ut[pl] : 0.0, sm.H[pl], sm.Sq[pr],
                                           sm.Un[pr], NV == 4 ? sm.Ut[pr] : 0.0, sm.H[pr], gm1, e);
             if (!ok) flag_nonphysical(in.status);
+            if constexpr (STASH) {
+                sm.F[NROW + tid] = e.H;
+                sm.F[NROW + NT + tid] = e.c;
+            }
         }
         double af[NV];
 #pragma unroll
@@ -1192,6 +1201,10 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
 #pragma unroll
             for (int q = 0; q < NV; ++q) Fh[q] = wh[q];
         } else {
+            if constexpr (STASH) {
+                e.H = sm.F[NROW + tid];
+                e.c = sm.F[NROW + NT + tid];
+            }
             back_project<NV>(e, wh, Fh);
         }
 
