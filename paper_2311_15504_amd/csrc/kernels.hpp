@@ -1222,9 +1222,15 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     }
     // ---- conservative difference and output; the cell's operands are
     // requested before the barriers so that their latency overlaps them
-    const long cell = c0 + tf;
-    const bool outc = gl < nlines && tf < TC && cell < n;
-    const long g = outc ? gidx(gl, cell) : 0;
+    // (the cell's position from the thread index again, through an empty
+    // asm, rather than held through the reconstruction)
+    int ot = tid;
+    asm volatile("" : "+v"(ot));
+    const int otf = lane_face(ot), otl = lane_line(ot);
+    const long ogl = line0 + otl;
+    const long cell = c0 + otf;
+    const bool outc = ogl < nlines && otf < TC && cell < n;
+    const long g = outc ? gidx(ogl, cell) : 0;
     double lp[NV], un[NV], us[NV];
     // the source, added by the 2D sweep that completes the operator: rho and
     // rho v of the cell
@@ -1257,7 +1263,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const int v = gvar(q);
-            double L = -((sm.F[q * NT + fpos(tl, tf + 1)] - sm.F[q * NT + fpos(tl, tf)]) * in.ih);
+            double L = -((sm.F[q * NT + fpos(otl, otf + 1)] - sm.F[q * NT + fpos(otl, otf)]) * in.ih);
             if (so.Lprev) L = lp[q] + L;
             if (SRC && in.grav != 0.0) {
                 if (v == 2) L = L + in.grav * s_rho;
