@@ -117,6 +117,23 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// The same reduction with the lane permutation formed at each call (the lane
+// index passes an empty asm), for callers inside long loops, where the
+// compiler would otherwise hold the six permutation indices through the loop.
+__device__ __forceinline__ double wave_max_local(double v)
+{
+    int lane = (int)__lane_id();
+    asm volatile("" : "+v"(lane));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int src = (lane ^ off) << 2;
+        const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(v));
+        const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(v));
+        v = fmax(v, __hiloint2double(hi, lo));
+    }
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Small utility kernels
 // ---------------------------------------------------------------------------
@@ -1364,7 +1381,7 @@ __device__ __forceinline__ double block_max_speed(const double* __restrict__ U, 
         if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(mo)) flag_nonphysical(status);
         m = fmax(m, fabs(u) + sqrt((gamma * p) * ir));
     }
-    m = wave_max(m);
+    m = wave_max_local(m);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
     double r = red[0];
