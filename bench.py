@@ -684,6 +684,178 @@ def traffic_summary(fetch_dir, write_dir, valu_dir, copy_mib, command):
     return "\n".join(lines)
 
 
+def _sweep_counters(dirs):
+    """Counter values of the order-17 2D sweeps from rocprofv3 --pmc runs:
+    {"x"|"y": {counter: [value per dispatch]}} and each sweep's dispatch record."""
+    import csv
+    import glob
+    vals = {"x": {}, "y": {}}
+    meta = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                k = row["Kernel_Name"]
+                if "k_euler_sweep<4, 9, 0" in k:
+                    w = "x"
+                elif "k_euler_sweep<4, 9, 1" in k:
+                    w = "y"
+                else:
+                    continue
+                vals[w].setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+                meta[w] = (int(row["Scratch_Size"]), int(row["LDS_Block_Size"]))
+    return vals, meta
+
+
+def stall_summary(dirs, command):
+    """Markdown table of the stall counters of the two order-17 sweeps from four
+    rocprofv3 --pmc runs of bench.py (dirs, in the order of the command: the SQ
+    issue and wait group, the LDS group, latency and occupancy, the
+    instruction mix); averages over the sweep launches."""
+    vals, meta = _sweep_counters(dirs)
+
+    def m(w, c):
+        v = vals[w][c]
+        return sum(v) / len(v)
+
+    def row(name, f):
+        return "| %s | %s | %s |" % (name, f("x"), f("y"))
+
+    def share(c):
+        return lambda w: "%.1f%%" % (100.0 * m(w, c) / m(w, "SQ_WAVE_CYCLES"))
+
+    def frac(w, c):
+        return 100.0 * m(w, c) / m(w, "SQ_INSTS_VALU")
+
+    mix = ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+           "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64")
+    lines = ["# Stall counters: 2D Euler 2048x2048, ENO-MR order 17, sweep kernels", "",
+             "Commands (repository root on one MI355X; one counter group per run, averages over the sweep launches):",
+             "", "```", command, "```", "",
+             "Per-wave shares are the SQ counters (wave-cycles summed over the waves) divided by SQ_WAVE_CYCLES; the",
+             "derived counters (LdsUtil, LDSBankConflict, VALUUtilization, LdsLatency, VmemLatency, MeanOccupancyPerCU)",
+             "are rocprofv3's own expressions. Scratch and LDS sizes are the dispatch records'.", "",
+             "| counter | x faces (completes the stage) | y faces |", "|---|---|---|",
+             row("waves per launch", lambda w: "%d" % m(w, "SQ_WAVES")),
+             row("scratch bytes per lane, LDS bytes per workgroup", lambda w: "%d, %d" % meta[w]),
+             row("mean waves resident per CU (of 16)", lambda w: "%.1f" % m(w, "MeanOccupancyPerCU")),
+             row("share of a wave's cycles issuing VALU (SQ_ACTIVE_INST_VALU)", share("SQ_ACTIVE_INST_VALU")),
+             row("issuing any instruction (SQ_ACTIVE_INST_ANY)", share("SQ_ACTIVE_INST_ANY")),
+             row("ready, another wave issues (SQ_WAIT_INST_ANY)", share("SQ_WAIT_INST_ANY")),
+             row("waiting on memory, LDS or a barrier (SQ_WAIT_ANY)", share("SQ_WAIT_ANY")),
+             row("lanes active per VALU instruction (VALUUtilization)", lambda w: "%.1f%%" % m(w, "VALUUtilization")),
+             row("LDS busy (LdsUtil)", lambda w: "%.1f%%" % m(w, "LdsUtil")),
+             row("LDS stalled on bank conflicts (LDSBankConflict, % of GPU time)",
+                 lambda w: "%.1f%%" % m(w, "LDSBankConflict")),
+             row("LDS latency (cycles per instruction)", lambda w: "%.0f" % m(w, "LdsLatency")),
+             row("vector memory latency (cycles per instruction)", lambda w: "%.0f" % m(w, "VmemLatency")),
+             row("VALU wave-instructions per launch", lambda w: "%.4g" % m(w, "SQ_INSTS_VALU")),
+             row("of which FP64 FMA / add / mul", lambda w: "%.1f%% / %.1f%% / %.1f%%" % tuple(frac(w, c) for c in mix[:3])),
+             row("of which integer (32 / 64 bit)", lambda w: "%.1f%% / %.1f%%" % tuple(frac(w, c) for c in mix[3:])),
+             row("of which other (compares, selects, min/max, moves, divide and square-root steps)",
+                 lambda w: "%.1f%%" % (100.0 - sum(frac(w, c) for c in mix))),
+             row("LDS instructions per launch", lambda w: "%.4g" % m(w, "SQ_INSTS_LDS")), ""]
+    return "\n".join(lines)
+
+
+def _kernel_table(stats_dir, n):
+    import csv
+    import glob
+    f = glob.glob(os.path.join(stats_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit("no kernel_stats.csv under %s" % stats_dir)
+    rows = sorted(csv.DictReader(open(f[0])), key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | average (us) | min (us) | max (us) | total (ms) | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:n]:
+        out.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f | %.2f |" % (
+            r["Name"][:90], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+    return out
+
+
+def legs_summary(kind, stats_dir, live_json, command, fetch_dir=None, write_dir=None, copy_mib=1024):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run of bench.py's
+    batched and adjoint legs (kind "batch") or scalar leg (kind "scalar", with
+    the HBM bytes of its two sweeps from FETCH_SIZE and WRITE_SIZE runs scaled
+    by the calibration copy of copy_mib MiB)."""
+    live = json.loads(open(live_json).read().strip().splitlines()[-1])
+    lines = []
+    if kind == "batch":
+        b1, b2, ad = live["batched"], live["batched_2d"], live["adjoint"]
+        shapes = ", ".join("%s %.2f" % (k, v) for k, v in b2["autotune_ms_per_step"].items())
+        lines = ["# Kernel time summary: batched 1D and 2D workloads and the 1D adjoint", "",
+                 "Command (repository root on one MI355X; rocprofv3 writes under gpurun_out/):", "", "```", command,
+                 "```", "",
+                 "The run makes one step of the 2D workload, the batched 1D workload (4096 problems, autotune of the tile",
+                 "width, one timed graph launch of 100 steps, then per-problem runs of a 64-problem sample), the batched 2D",
+                 "workload (1024 problems, autotune of the tile shape, 20 steps stage by stage, then a 64-problem sample) and",
+                 "the adjoint workload (N = 8192, order 9, 100 steps, checkpoint every 20).  Figures of the same run, under",
+                 "the profiler:", "",
+                 "- batched 1D: %.2e cell-updates/s, %.1f ms for the timed launch, %.1fx per-problem launches, tile width %d;"
+                 % (b1["value"], b1["ms"], b1["speedup_vs_per_problem"], b1["tile_faces"]),
+                 "- batched 2D: %.2e cell-updates/s, %.1f ms for the 20 timed steps, %.1fx per-problem launches, tiles "
+                 "%dx%d faces x lines (one-step times per shape, ms: %s);"
+                 % (b2["value"], b2["ms"], b2["speedup_vs_per_problem"], b2["tile2d"][0], b2["tile2d"][1], shapes),
+                 "- adjoint: forward %.2f ms, backward %.2f ms, ratio %.2f." % (ad["forward_ms"], ad["backward_ms"],
+                                                                              ad["adjoint_fwd_ratio"]), "",
+                 "The profiler traces every launch, which slows the many small per-problem launches far more than the",
+                 "batched launches: the speedups above are larger than in unprofiled runs.  The 1D persistent kernel has one",
+                 "launch per graph replay (autotune of three widths, warm-up, the timed launch), so its average mixes the",
+                 "short and the long launches (see min and max).  The 2D problems advance stage by stage: per order, one",
+                 "`k_batch2_alpha` and one `k_batch2_sweep` per direction, the four orders as parallel graph branches, so",
+                 "those kernels' durations include the time they share the GPU with the other orders' kernels.", ""]
+        lines += _kernel_table(stats_dir, 20)
+    else:
+        import csv
+        import glob
+        sc = live["scalar"]
+        o5, o17 = sc["order5"], sc["order17"]
+
+        def per_dispatch(d, counter):
+            vals = {}
+            for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+                for row in csv.DictReader(open(f)):
+                    if row["Counter_Name"] != counter:
+                        continue
+                    k = row["Kernel_Name"]
+                    key = ("dpp" if "k_scalar_sweep_dpp<3>" in k else "lds" if "k_scalar_sweep<9, 64>" in k
+                           else "copy" if "copyBuffer" in k else None)
+                    if key:
+                        per = vals.setdefault(key, {})
+                        per[row["Dispatch_Id"]] = per.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+            out = {k: sum(v.values()) / len(v) for k, v in vals.items() if k != "copy"}
+            out["copy"] = max(vals["copy"].values())
+            return out
+
+        fe, wr = per_dispatch(fetch_dir, "FETCH_SIZE"), per_dispatch(write_dir, "WRITE_SIZE")
+        kib = copy_mib * 1024.0
+        ff, fw = kib / fe["copy"], kib / wr["copy"]
+        comp = 21.3333 * (1 << 27)
+        lines = ["# Scalar sweeps: 1D advection, LF split, 2^27 nodes, ENO-MR orders 5 and 17", "",
+                 "Commands (repository root on one MI355X; rocprofv3 writes under gpurun_out/):", "", "```", command,
+                 "```", "",
+                 "The scalar leg of bench.py: seeded sines + step on [-1, 1], periodic, SSP-RK3 at CFL 0.5, one warm-up",
+                 "step and 5 timed steps per order.  The run also makes one step of the 2D workload (its kernels are in the",
+                 "table, not part of this path).  Live figures of the same run (under the profiler): order 5",
+                 "%.2e cell-updates/s, %.1f us per sweep; order 17 %.2e cell-updates/s," % (o5["value"], o5["sweep_us"],
+                                                                                        o17["value"]),
+                 "%.1f us per sweep.  The alpha pass of advection takes |a| without reading the line." % o17["sweep_us"],
+                 ""]
+        lines += _kernel_table(stats_dir, 10)
+        lines += ["", "HBM traffic per launch (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, each scaled by the factor that",
+                  "maps the counter on the copy kernel of torch's copy of a %d MiB float64 tensor in the same run to" % copy_mib,
+                  "%d MiB: fetch %.4f, write %.4f).  Compulsory bytes per launch: 16 B per node at the first stage"
+                  % (copy_mib, ff, fw),
+                  "(read U, write U^(1)), 24 B at the other two (read U^(s), U^n, write); 21.3 B on average, %.3e B" % comp,
+                  "per launch.", "",
+                  "| kernel | FETCH KiB | WRITE KiB | HBM bytes (scaled) | / compulsory |", "|---|---|---|---|---|"]
+        for key, name in (("dpp", "order 5 (lanes share windows) `k_scalar_sweep_dpp<3>`"),
+                          ("lds", "order 17 (LDS windows) `k_scalar_sweep<9, 64>`")):
+            by = (fe[key] * ff + wr[key] * fw) * 1024.0
+            lines.append("| %s | %.0f | %.0f | %.3e | %.2f |" % (name, fe[key], wr[key], by, by / comp))
+    lines.append("")
+    return "\n".join(lines)
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -768,7 +940,24 @@ def main():
                     help="write the kernel-time summary of a rocprofv3 --stats run of bench.py --no-replay "
                          "(LIVE_JSON: its printed line) to stdout and exit")
     ap.add_argument("--stats-command", default="", help="command text recorded in the kernel-time summary")
+    ap.add_argument("--stall-summary", nargs=4, metavar=("ISSUE_DIR", "LDS_DIR", "LATENCY_DIR", "MIX_DIR"),
+                    help="write the stall-counter summary of the order-17 sweeps from four rocprofv3 --pmc runs "
+                         "to stdout and exit")
+    ap.add_argument("--legs-summary", nargs=2, metavar=("KIND", "STATS_DIR"),
+                    help="write the kernel-time summary of the batched/adjoint legs (KIND batch) or the scalar leg "
+                         "(KIND scalar, with --legs-traffic) of a rocprofv3 --stats run to stdout and exit")
+    ap.add_argument("--legs-live", default="", help="the line bench.py printed in the --legs-summary run")
+    ap.add_argument("--legs-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None)
+    ap.add_argument("--summary-command", default="", help="command text recorded in a stall or legs summary")
     args = ap.parse_args()
+    if args.stall_summary:
+        print(stall_summary(args.stall_summary, args.summary_command))
+        return
+    if args.legs_summary:
+        kind, sdir = args.legs_summary
+        fd, wd = args.legs_traffic if args.legs_traffic else (None, None)
+        print(legs_summary(kind, sdir, args.legs_live, args.summary_command, fd, wd))
+        return
     if args.stats_summary:
         print(stats_summary(args.stats_summary[0], args.order, args.stats_command, args.stats_summary[1]))
         return
