@@ -870,10 +870,14 @@ __device__ __forceinline__ double fallback_window(const Eig& e, const double (&A
 // (rho, n, m, E) so that the same x-normal formulas apply.  NCL >= TF+2R-1 is
 // the number of cells per line the LDS holds.  VAR selects the operator variant (VAR_CHAR,
 // VAR_COMPONENT, VAR_FIELD).  All threads of the block must call it.
-template <int NV, int R, int DIR, int TF, int TL, int NCL, int VAR = VAR_CHAR, bool LOOPED = false>
+template <int NV, int R, int DIR, int TF, int TL, int NCL, int VAR = VAR_CHAR, bool LOOPED = false,
+          bool SPEED = false>
 __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so, long line0, long c0,
-                                           SweepLds<NV, NCL * TL, TF * TL>& sm)
+                                           SweepLds<NV, NCL * TL, TF * TL>& sm, double* smax = nullptr)
 {
+    // SPEED (1D Euler): fold the largest |u| + c of the cells this thread
+    // stores into *smax, with the expressions of block_max_speed, so that the
+    // caller has the next stage's alpha without another pass over the line.
     // LOOPED: the caller runs tiles in a loop.  The thread index then passes
     // an empty asm, so that the indices derived from it are formed per tile
     // rather than hoisted out of the loop and held (spilled) through it.
@@ -1277,6 +1281,7 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
     phase_stamp<NV, DIR>(7);   // face fluxes written
     __syncthreads();
     if (outc) {
+        double ov[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const int v = gvar(q);
@@ -1286,8 +1291,17 @@ __device__ __forceinline__ void sweep_tile(const SweepIn& in, const StageOut& so
                 if (v == 2) L = L + in.grav * s_rho;
                 if (v == 3) L = L + in.grav * s_rv;
             }
-            if (so.stage == 0) so.out[v * plane + g] = L;
-            else so.out[v * plane + g] = rk_combine(so.stage, un[q], us[q], L, dt);
+            ov[q] = so.stage == 0 ? L : rk_combine(so.stage, un[q], us[q], L, dt);
+            so.out[v * plane + g] = ov[q];
+        }
+        if constexpr (SPEED && NV == 3) {
+            const double rho = ov[0], mo = ov[1], E = ov[2];
+            const double ir = 1.0 / rho;
+            const double u = mo * ir;
+            const double ke = 0.5 * (mo * u);
+            const double p = gm1 * (E - ke);
+            if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(mo)) flag_nonphysical(in.status);
+            *smax = fmax(*smax, fabs(u) + sqrt((gamma * p) * ir));
         }
     }
     phase_stamp<NV, DIR>(8);   // output stored
@@ -1364,6 +1378,20 @@ __global__ void k_set_batch_params(BatchParams* p, double cfl, long nsteps, int*
     }
 }
 
+// The largest of the NT threads' values; every thread gets it.
+template <int NT>
+__device__ __forceinline__ double block_max(double m, double* red)
+{
+    m = wave_max_local(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) r = fmax(r, red[w]);
+    __syncthreads();
+    return r;
+}
+
 // Largest |u| + c over a 1D Euler line, by every thread of the workgroup (NT
 // threads); all threads get the result.
 template <int NT>
@@ -1381,14 +1409,7 @@ __device__ __forceinline__ double block_max_speed(const double* __restrict__ U, 
         if (!(rho > 0.0) || !(p > 0.0) || !isfinite(E) || !isfinite(mo)) flag_nonphysical(status);
         m = fmax(m, fabs(u) + sqrt((gamma * p) * ir));
     }
-    m = wave_max_local(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    double r = red[0];
-#pragma unroll
-    for (int w = 1; w < NT / 64; ++w) r = fmax(r, red[w]);
-    __syncthreads();
-    return r;
+    return block_max<NT>(m, red);
 }
 
 // A pointer that every lane holds the same value of, as a scalar.
@@ -1412,11 +1433,15 @@ __device__ __forceinline__ void run_problem(const BatchProb P, const BatchParams
     double* const u0 = uniform_ptr(P.U);
     double* const u1 = uniform_ptr(P.U1);
     double* const u2 = uniform_ptr(P.U2);
+    // the alpha of a stage's input: one pass over the line for the run's
+    // first stage, then the stage before folds it into its output phase
+    double a_next = 0.0;
+    bool known = false;
     for (long step = 0; step < prm.nsteps; ++step) {
         for (int stage = 1; stage <= 3; ++stage) {
             const double* Us = stage == 1 ? u0 : (stage == 2 ? u1 : u2);
             double* out = stage == 1 ? u1 : (stage == 2 ? u2 : u0);
-            const double a = block_max_speed<TF>(Us, P.n, P.gamma, status, red);
+            const double a = known ? a_next : block_max_speed<TF>(Us, P.n, P.gamma, status, red);
             if (threadIdx.x == 0) {
                 *s_alpha = a;
                 if (stage == 1) *s_dt = prm.cfl / (a * P.ih);
@@ -1442,10 +1467,15 @@ __device__ __forceinline__ void run_problem(const BatchProb P, const BatchParams
             so.stage = stage;
             // a tile's staging overwrites the face fluxes the previous tile's
             // output reads
+            // each thread's running maximum waits in its own LDS slot, not in
+            // a register held through the tile loop
+            double smax = 0.0;
             for (long c0 = 0; c0 < P.n; c0 += TF - 1) {
-                sweep_tile<3, R, 0, TF, 1, TF + 17, VAR_CHAR, true>(in, so, 0, c0, sm);
+                sweep_tile<3, R, 0, TF, 1, TF + 17, VAR_CHAR, true, true>(in, so, 0, c0, sm, &smax);
                 __syncthreads();
             }
+            a_next = block_max<TF>(smax, red);
+            known = true;
         }
     }
 }
